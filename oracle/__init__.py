@@ -1,0 +1,291 @@
+"""FP64 CPU oracle for the collisionless-stellar-hydrodynamics sweep.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP implementation in ``paper_1210_5246_amd``; neither imports the
+other.
+
+The arithmetic lives in ``cshoracle.c`` (plain C, FP64, built by the host
+compiler with ``-O2 -ffp-contract=off``, no fast-math, OpenMP over rows).
+This module is the ctypes shim plus a few drivers written directly from the
+paper:
+
+* ``run_cfl``        -- the time loop: dt = C / s from the state at the start
+                        of each step (the paper gives no formula; reading R8 of
+                        ``cshoracle.c``), optionally clipped to an end time;
+* ``dense_jacobian`` -- brute-force central-difference Jacobian of one step at
+                        frozen dt (used to pin the adjoint).
+
+Arrays are numpy float64, structure-of-arrays ``[6, ny, nx]`` (1-D: ``[6, n]``),
+conserved U = (rho, rho u, rho v, Exx, Exy, Eyy), primitive
+W = (rho, u, v, Pxx, Pxy, Pyy).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cshoracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# A test may point the shim at a differently built copy (planted-mistake checks).
+_LIB_OVERRIDE = os.environ.get("CSH_ORACLE_LIB")
+
+BC_PERIODIC = 0
+BC_OUTFLOW = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the host C compiler (gcc)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+               "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("bcx", ctypes.c_int), ("bcy", ctypes.c_int),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("vc", ctypes.c_double), ("rc", ctypes.c_double)]
+
+
+@dataclass
+class Grid:
+    """Uniform grid.  ny == 1 selects the 1-D scheme."""
+    nx: int
+    ny: int = 1
+    dx: float = 1.0
+    dy: float = 1.0
+    bcx: int = BC_PERIODIC
+    bcy: int = BC_PERIODIC
+    x0: float = 0.0
+    y0: float = 0.0
+    vc: float = 0.0   # flat-rotation-curve external potential (0: none)
+    rc: float = 0.0
+
+    def c(self) -> _Grid:
+        return _Grid(self.nx, self.ny, self.dx, self.dy, self.bcx, self.bcy,
+                     self.x0, self.y0, self.vc, self.rc)
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = ctypes.CDLL(_LIB_PATH)
+        G = ctypes.POINTER(_Grid)
+        L.orc_step.argtypes = [G, ctypes.c_double, _D, _D]
+        L.orc_step_cells.argtypes = [G, ctypes.c_double, _D, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64), _D]
+        L.orc_fluxes.argtypes = [G, ctypes.c_double, _D, _D, _D]
+        L.orc_max_signal_speed.argtypes = [G, _D]
+        L.orc_max_signal_speed.restype = ctypes.c_double
+        L.orc_physical.argtypes = [G, _D]
+        L.orc_cons_field.argtypes = [ctypes.c_int64, _D, _D]
+        L.orc_prim_field.argtypes = [ctypes.c_int64, _D, _D]
+        for name in ("orc_cons", "orc_prim", "orc_flux_x", "orc_flux_y"):
+            getattr(L, name).argtypes = [_D, _D]
+        for name in ("orc_jac_x", "orc_jac_y"):
+            getattr(L, name).argtypes = [_D, _D]
+        for name in ("orc_eigen_x", "orc_eigen_y"):
+            getattr(L, name).argtypes = [_D, _D, _D, _D]
+        L.orc_mc.argtypes = [ctypes.c_double] * 3
+        L.orc_mc.restype = ctypes.c_double
+        L.orc_limited_slope.argtypes = [ctypes.c_int, _D, _D, _D, _D]
+        L.orc_trace.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, _D, _D]
+        L.orc_hll.argtypes = [ctypes.c_int, _D, _D, _D]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _vec(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+# ---- pointwise pieces (for the pin tests) -------------------------------------------
+
+def cons(w) -> np.ndarray:
+    w = _vec(w); out = np.empty(6); lib().orc_cons(_p(w), _p(out)); return out
+
+
+def prim(U) -> np.ndarray:
+    U = _vec(U); out = np.empty(6); lib().orc_prim(_p(U), _p(out)); return out
+
+
+def flux(direction: int, U) -> np.ndarray:
+    U = _vec(U); out = np.empty(6)
+    (lib().orc_flux_x if direction == 0 else lib().orc_flux_y)(_p(U), _p(out))
+    return out
+
+
+def jacobian(direction: int, w) -> np.ndarray:
+    w = _vec(w); out = np.empty((6, 6))
+    (lib().orc_jac_x if direction == 0 else lib().orc_jac_y)(_p(w), _p(out))
+    return out
+
+
+def eigen(direction: int, w):
+    """(lam[6], R[6,6] with eigenvectors in columns, L[6,6] with them in rows)."""
+    w = _vec(w); lam = np.empty(6); R = np.empty((6, 6)); L = np.empty((6, 6))
+    (lib().orc_eigen_x if direction == 0 else lib().orc_eigen_y)(_p(w), _p(lam), _p(R), _p(L))
+    return lam, R, L
+
+
+def mc(dl: float, dc: float, dr: float) -> float:
+    return lib().orc_mc(dl, dc, dr)
+
+
+def limited_slope(direction: int, wm, w0, wp) -> np.ndarray:
+    wm, w0, wp = _vec(wm), _vec(w0), _vec(wp); out = np.empty(6)
+    lib().orc_limited_slope(direction, _p(wm), _p(w0), _p(wp), _p(out))
+    return out
+
+
+def trace(direction: int, w, dwm, k: float):
+    """(w_lo, w_hi): states on the low (i-1/2) and high (i+1/2) faces."""
+    w, dwm = _vec(w), _vec(dwm); lo = np.empty(6); hi = np.empty(6)
+    lib().orc_trace(direction, _p(w), _p(dwm), k, _p(lo), _p(hi))
+    return lo, hi
+
+
+def hll(direction: int, wl, wr) -> np.ndarray:
+    wl, wr = _vec(wl), _vec(wr); out = np.empty(6)
+    lib().orc_hll(direction, _p(wl), _p(wr), _p(out))
+    return out
+
+
+# ---- fields ----------------------------------------------------------------------------
+
+def cons_field(W: np.ndarray) -> np.ndarray:
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    U = np.empty_like(W)
+    lib().orc_cons_field(W[0].size, _p(W), _p(U))
+    return U
+
+
+def prim_field(U: np.ndarray) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    W = np.empty_like(U)
+    lib().orc_prim_field(U[0].size, _p(U), _p(W))
+    return W
+
+
+def _check(g: Grid, U: np.ndarray) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    if U.size != 6 * g.nx * g.ny:
+        raise ValueError("state has the wrong size for the grid")
+    return U
+
+
+def step(g: Grid, dt: float, U: np.ndarray) -> np.ndarray:
+    U = _check(g, U); out = np.empty_like(U)
+    if lib().orc_step(ctypes.byref(g.c()), dt, _p(U), _p(out)) != 0:
+        raise ValueError("bad grid")
+    return out
+
+
+def step_cells(g: Grid, dt: float, U: np.ndarray, cells) -> np.ndarray:
+    """Updated conserved state of the listed cells (flat index j*nx+i): [len(cells), 6]."""
+    U = _check(g, U)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.empty((cells.size, 6))
+    if lib().orc_step_cells(ctypes.byref(g.c()), dt, _p(U), cells.size,
+                            cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out)) != 0:
+        raise ValueError("bad grid")
+    return out
+
+
+def fluxes(g: Grid, dt: float, U: np.ndarray):
+    """(Fx [6, ny, nx+1], Fy [6, ny+1, nx] or None in 1-D)."""
+    U = _check(g, U)
+    Fx = np.empty((6, g.ny, g.nx + 1))
+    Fy = np.empty((6, g.ny + 1, g.nx)) if g.ny > 1 else np.empty(6)
+    if lib().orc_fluxes(ctypes.byref(g.c()), dt, _p(U), _p(Fx), _p(Fy)) != 0:
+        raise ValueError("bad grid")
+    return Fx, (Fy if g.ny > 1 else None)
+
+
+def max_signal_speed(g: Grid, U: np.ndarray) -> float:
+    U = _check(g, U)
+    return lib().orc_max_signal_speed(ctypes.byref(g.c()), _p(U))
+
+
+def physical(g: Grid, U: np.ndarray) -> bool:
+    U = _check(g, U)
+    return bool(lib().orc_physical(ctypes.byref(g.c()), _p(U)))
+
+
+# ---- drivers ---------------------------------------------------------------------------
+
+def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
+            t_end: float | None = None, max_steps: int = 100000):
+    """Advance with dt = cfl / s (s from the state at the start of each step).
+
+    Stops after ``nsteps`` steps, or when ``t_end`` is reached (the last step is
+    clipped to land on it).  Returns (U, list of dt).
+    """
+    U = _check(g, U).copy()
+    dts, t = [], 0.0
+    while True:
+        if nsteps is not None and len(dts) >= nsteps:
+            break
+        if t_end is not None and t >= t_end:
+            break
+        if len(dts) >= max_steps:
+            raise RuntimeError("too many steps")
+        dt = cfl / max_signal_speed(g, U)
+        if t_end is not None and t + dt > t_end:
+            dt = t_end - t
+        U = step(g, dt, U)
+        dts.append(dt)
+        t += dt
+    return U, dts
+
+
+def run_dts(g: Grid, U: np.ndarray, dts) -> np.ndarray:
+    """Advance with a given list of timesteps."""
+    U = _check(g, U).copy()
+    for dt in dts:
+        U = step(g, dt, U)
+    return U
+
+
+def dense_jacobian(g: Grid, dt: float, U: np.ndarray, rel: float = 1e-7, floor: float = 1e-3):
+    """J[a, b] = d step(U)_a / d U_b by central differences at frozen dt.
+
+    The step of component b is h_b = rel * max(|U_b|, floor).
+    Flattened SoA order (the order of ``U.ravel()``).
+    """
+    U = _check(g, U)
+    flat = U.ravel()
+    n = flat.size
+    J = np.empty((n, n))
+    for b in range(n):
+        h = rel * max(abs(flat[b]), floor)
+        up = flat.copy(); up[b] += h
+        dn = flat.copy(); dn[b] -= h
+        J[:, b] = (step(g, dt, up.reshape(U.shape)).ravel()
+                   - step(g, dt, dn.reshape(U.shape)).ravel()) / (2.0 * h)
+    return J

@@ -1,0 +1,57 @@
+/*
+ * FP64 CPU oracle for the collisionless-stellar-hydrodynamics sweep.
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product path.
+ *
+ * Arrays at this interface are structure-of-arrays, [6][ny][nx], x fastest,
+ * in the variable order
+ *   conserved U = (rho, rho u, rho v, Exx, Exy, Eyy),  E_ij = P_ij + rho u_i u_j
+ *   primitive W = (rho, u, v, Pxx, Pxy, Pyy).
+ * ny == 1 selects the one-dimensional scheme (no y terms at all).
+ */
+#ifndef CSHORACLE_H
+#define CSHORACLE_H
+
+#include <stdint.h>
+
+#define ORC_BC_PERIODIC 0
+#define ORC_BC_OUTFLOW 1
+
+typedef struct {
+    int nx, ny;
+    double dx, dy;
+    int bcx, bcy;
+    double x0, y0; /* lower-left domain corner; cell centre x0 + (i + 1/2) dx */
+    double vc, rc; /* external flat-rotation-curve potential; vc == 0: none */
+} orc_grid;
+
+void orc_cons(const double w[6], double U[6]);
+void orc_prim(const double U[6], double w[6]);
+void orc_flux_x(const double U[6], double F[6]);
+void orc_flux_y(const double U[6], double G[6]);
+void orc_jac_x(const double w[6], double A[6][6]);
+void orc_jac_y(const double w[6], double B[6][6]);
+void orc_eigen_x(const double w[6], double lam[6], double R[6][6], double L[6][6]);
+void orc_eigen_y(const double w[6], double lam[6], double R[6][6], double L[6][6]);
+double orc_mc(double dl, double dc, double dr);
+void orc_limited_slope(int dir, const double wm[6], const double w0[6], const double wp[6],
+                       double dwm[6]);
+void orc_trace(int dir, const double w[6], const double dwm[6], double k, double w_lo[6],
+               double w_hi[6]);
+void orc_hll(int dir, const double wl[6], const double wr[6], double flux[6]);
+
+/* One step U -> Unew (may not alias), timestep dt.  Returns 0, or -1 on a bad grid. */
+int orc_step(const orc_grid *g, double dt, const double *U, double *Unew);
+/* The step for selected cells only: cells[s] = j * nx + i, out[s][6] (cell-major). */
+int orc_step_cells(const orc_grid *g, double dt, const double *U, int64_t ncells,
+                   const int64_t *cells, double *out);
+/* Face fluxes of the step: Fx [6][ny][nx+1] (column i = face i-1/2),
+ * Fy [6][ny+1][nx] (row j = face j-1/2); Fy unused in 1-D. */
+int orc_fluxes(const orc_grid *g, double dt, const double *U, double *Fx, double *Fy);
+double orc_max_signal_speed(const orc_grid *g, const double *U);
+int orc_physical(const orc_grid *g, const double *U);
+/* Whole-field conversions, SoA [6][n]. */
+void orc_cons_field(int64_t n, const double *W, double *U);
+void orc_prim_field(int64_t n, const double *U, double *W);
+
+#endif

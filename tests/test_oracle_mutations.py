@@ -1,0 +1,78 @@
+"""Planted mistakes in the oracle must fail its pins.
+
+Each case copies the oracle's C source, plants one plausible mistake (a
+dropped term, a wrong sign, a swapped index, the paper's printed form where a
+reading corrects it), builds the copy on the CPU and runs the pin tests
+against it.  A mutant that passes every pin would mean the pins do not
+constrain that part of the oracle.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "cshoracle.c")
+
+MUTANTS = {
+    # eq. (28) as printed: 1/2 - max(lam0, 0) k instead of 1/2 + min(lam0, 0) k
+    "eq28_printed_sign": ("w_lo[m] = w[m] - (0.5 + k * fmin(lam0, 0.0)) * dwm[m];",
+                          "w_lo[m] = w[m] - (0.5 - k * fmax(lam0, 0.0)) * dwm[m];"),
+    # eq. (31) not added (CTU-only tracing with an HLL flux)
+    "eq31_dropped": ("for (int m = 0; m < NV; ++m) w_hi[m] -= k * ((lam[a] - lamM) * pa) * R[m][a];",
+                     "(void)0;"),
+    # MC limiter without the extremum clause
+    "mc_no_extremum_clause": ("if (dl * dr <= 0.0) return 0.0;", ""),
+    # transverse predictor with the wrong sign
+    "transverse_sign": ("xlo[s + m] -= ky * Bdw[m];", "xlo[s + m] += ky * Bdw[m];"),
+    # transverse predictor dropped on the y faces
+    "transverse_dropped_y": ("yhi[s + m] -= kx * Adw[m];", "(void)Adw;"),
+    # flux: Pxy u term dropped from the Exy flux
+    "flux_exy_term": ("F[4] = U[4] * u + pxy * u + pxx * v;", "F[4] = U[4] * u + pxx * v;"),
+    # flux: y-flux of Exx with the wrong stress component
+    "flux_y_exx": ("G[3] = U[3] * v + 2.0 * pxy * u;", "G[3] = U[3] * v + 2.0 * w[IXX] * u;"),
+    # left eigenvector with a sign error
+    "left_eigvec_sign": ("{0.0, q / (2.0 * c), -1.0 / (2.0 * c), -pxy / (2.0 * pxx * pxx), 1.0 / (2.0 * pxx), 0.0},",
+                         "{0.0, -q / (2.0 * c), -1.0 / (2.0 * c), -pxy / (2.0 * pxx * pxx), 1.0 / (2.0 * pxx), 0.0},"),
+    # Jacobian as printed in eq. (16): no transverse compression term Pyy u_x
+    "jacobian_printed": ("A[IYY][IU] = pyy;", "A[IYY][IU] = 0.0;"),
+    # y Jacobian with a transposed entry
+    "jac_y_index": ("B[IXY][IU] = pyy;", "B[IU][IXY] = pyy;"),
+    # HLL with the wrong sign of the dissipation term
+    "hll_sign": ("flux[m] = (sr * Fl[m] - sl * Fr[m] + sl * sr * (Ur[m] - Ul[m])) / (sr - sl);",
+                 "flux[m] = (sr * Fl[m] - sl * Fr[m] - sl * sr * (Ur[m] - Ul[m])) / (sr - sl);"),
+    # update with the y flux difference scaled by dx
+    "update_dy": ("const double cx = dt / g->dx, cy = twod ? dt / g->dy : 0.0;",
+                  "const double cx = dt / g->dx, cy = twod ? dt / g->dx : 0.0;"),
+    # kick on the wrong velocity component
+    "kick_component": ("w[IV] += dt * ay;", "w[IV] += dt * ax;"),
+    # CFL rate without the y term
+    "cfl_no_y": ("if (twod) s += (fabs(w[IV]) + sqrt(3.0 * w[IYY] / w[IR])) / g->dy;", ""),
+    # outflow ghost copies the second cell instead of the edge cell.  (Reflecting
+    # ghost -2 alone would be an equivalent mutant: with MC the slope of ghost
+    # -1 is zero whatever ghost -2 holds.)
+    "bc_outflow": ("if (i < 0) return 0;", "if (i < 0) return 1;"),
+    # periodic wrap off by one
+    "bc_periodic": ("return (r < 0) ? r + n : r;", "return (r < 0) ? r + n - 1 : r;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_fails_a_pin(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site not found uniquely: {name}"
+    mut = tmp_path / "cshoracle.c"
+    mut.write_text(src.replace(old, new))
+    for h in ("cshoracle.h",):
+        (tmp_path / h).write_text(open(os.path.join(ROOT, "oracle", h)).read())
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                    "-o", str(lib), str(mut), "-lm"], check=True, cwd=tmp_path)
+    env = dict(os.environ, CSH_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
