@@ -1,0 +1,186 @@
+/*
+ * cshydro -- collisionless stellar hydrodynamics on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the Godunov sweep for the Boltzmann moment equations (BME) of
+ * Mitchell, Vorobyov & Hensler, "Collisionless Stellar Hydrodynamics as an
+ * Efficient Alternative to N-body Methods" (arXiv:1210.5246):
+ *   continuity, momentum and second-moment equations, Sec. 2, eqs. (2)-(4),
+ *   closed with zero heat flux (Q_ijk = 0), advanced by the MUSCL-Hancock
+ *   scheme with characteristic tracing and an HLL Riemann flux of Sec. 3.3,
+ *   eqs. (10)-(32), on a uniform 1-D or 2-D grid, with the full symmetric 2-D
+ *   stress tensor.
+ *
+ * Conventions for every entry point:
+ *   - All state arrays are DEVICE pointers owned by the caller, structure of
+ *     arrays [6][ny][nx] with x fastest (1-D: ny = 1), contiguous, element type
+ *     double (CSH_F64) or float (CSH_F32) as chosen at init.
+ *       conserved U = (rho, rho u, rho v, Exx, Exy, Eyy), E_ij = P_ij + rho u_i u_j
+ *       primitive W = (rho, u, v, Pxx, Pxy, Pyy), P_ij = rho sigma^2_ij (Sec. 2)
+ *   - Work is enqueued on the HIP stream given at init and is asynchronous
+ *     unless a function says it synchronises.
+ *   - Return value: CSH_OK (0) or a negative CSH_ERR_* code; csh_last_error()
+ *     returns a message for the calling thread's last error.  No C++ exception
+ *     crosses this interface.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef CSHYDRO_H
+#define CSHYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSH_OK 0
+#define CSH_ERR_ARG (-1)         /* invalid argument (sizes, pointers, enum values)  */
+#define CSH_ERR_HIP (-2)         /* a HIP runtime call failed                         */
+#define CSH_ERR_NONPHYSICAL (-3) /* a state with rho <= 0, non-positive-definite stress or a
+                                    non-finite value was produced or supplied            */
+
+#define CSH_BC_PERIODIC 0 /* wrap-around ghost cells                                */
+#define CSH_BC_OUTFLOW 1  /* zero-gradient ghost cells (copy of the edge cell)      */
+
+#define CSH_F64 0
+#define CSH_F32 1
+
+typedef struct csh_grid csh_grid;
+typedef struct csh_batch csh_batch;
+
+const char *csh_last_error(void);
+
+/*
+ * Create a grid handle and convert primitive to conserved state.
+ * nx >= 1, ny >= 1 (ny == 1: one-dimensional scheme, no y terms); dx, dy > 0
+ * (dy unused in 1-D); bc_x, bc_y: CSH_BC_*; dtype: CSH_F64 or CSH_F32.
+ * W: device, primitive fields [6][ny][nx], read only.  U: device, receives the
+ * conserved state [6][ny][nx] (the definitions of Sec. 2).  stream: a
+ * hipStream_t (NULL: the null stream).  Synchronises; returns
+ * CSH_ERR_NONPHYSICAL (handle still created) if some cell of W has rho <= 0,
+ * Pxx <= 0, Pyy <= 0, Pxx Pyy - Pxy^2 <= 0 or a non-finite value.
+ * The handle owns small device scalars (and, once csh_adjoint_step is used,
+ * the adjoint workspace); free it with csh_destroy.
+ */
+int csh_init_state(csh_grid **h, int nx, int ny, double dx, double dy, int bc_x, int bc_y,
+                   int dtype, const void *W, void *U, void *stream);
+
+/*
+ * Fixed external potential of a flat rotation curve, Phi = vc^2/2 ln(R^2 + rc^2)
+ * centred on the coordinate origin (the analytic stand-in for the halo of
+ * Sec. 4.4), applied after every step as an exact operator-split kick
+ * u_i += dt a_i with a = -grad Phi, rho and P unchanged (Sec. 3.3, last
+ * paragraph).  (x0, y0) are the coordinates of the grid's lower-left corner:
+ * cell (i, j) is centred at (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy) (1-D: y = 0).
+ * vc == 0 switches the source off.
+ */
+int csh_set_potential(csh_grid *h, double vc, double rc, double x0, double y0);
+
+/*
+ * One sweep U -> U_new with timestep dt (host value): slopes, characteristic
+ * limiting and tracing, HLL flux at every face, the unsplit conservative update
+ * (Sec. 3.3, eqs. (19)-(32)) and the source kick if set.  U and U_new are
+ * distinct device buffers [6][ny][nx].  Also reduces the CFL rate of U_new on
+ * the device (read it with csh_last_signal_speed).  Asynchronous: a
+ * non-physical output is reported by the next synchronising call.
+ */
+int csh_step(csh_grid *h, double dt, const void *U, void *U_new);
+
+/*
+ * s = max over cells of (|u| + a_x)/dx + (|v| + a_y)/dy (1-D: (|u| + a_x)/dx),
+ * a_d = sqrt(3 P_dd / rho) (Sec. 3.2, eq. (8) with gamma = 3); the CFL
+ * timestep is C / s.  Reads U, synchronises, writes *s (host).
+ * Returns CSH_ERR_NONPHYSICAL if a cell of U, or an output of an earlier
+ * asynchronous call on this handle, was not physical.
+ */
+int csh_max_signal_speed(csh_grid *h, const void *U, double *s);
+
+/* s of the output of the last csh_step / csh_run_cfl (fused reduction, no pass
+ * over the state).  Synchronises; errors as csh_max_signal_speed. */
+int csh_last_signal_speed(csh_grid *h, double *s);
+
+/*
+ * The HLL face fluxes of the sweep of U with timestep dt (the time-centred
+ * fluxes the update of csh_step uses; no source term).  Fx: device
+ * [6][ny][nx+1], column i holds face i-1/2; Fy: device [6][ny+1][nx], row j
+ * holds face j-1/2 (ignored in 1-D, may be NULL).  Asynchronous.
+ */
+int csh_fluxes(csh_grid *h, double dt, const void *U, void *Fx, void *Fy);
+
+/*
+ * Advance nsteps steps with the timestep chosen on the device every step:
+ * dt_n = C / s_n (C = cfl, s_n the rate of the state at the start of the step),
+ * clipped so that the time, starting from 0 at this call, does not pass t_end
+ * (t_end <= 0: no clipping; steps after t_end is reached have dt = 0 and leave
+ * the state unchanged).  U: device state, updated in place on return (the
+ * steps alternate between U and U_work, a caller-owned device buffer of the
+ * same size).  dt_log: device array of nsteps doubles receiving each step's
+ * timestep, or NULL.  No host synchronisation between steps; the sequence is
+ * captured once as a HIP graph per (nsteps, buffers, cfl, t_end) and replayed.
+ */
+int csh_run_cfl(csh_grid *h, int nsteps, double cfl, double t_end, void *U, void *U_work,
+                double *dt_log);
+
+/*
+ * Adjoint of one sweep at frozen timestep dt:
+ *   lam = (d step_dt(U) / d U)^T lam_next,
+ * the exact transpose of the linearisation of csh_step about U (limiter and
+ * HLL branches fixed at U; at ties the subgradient of the first minimal
+ * argument), external kick included.  U, lam_next: device, read only;
+ * lam: device output; all [6][ny][nx] of the handle's dtype (CSH_F64 only).
+ * Does not touch the handle's CFL state.  The first call allocates a workspace
+ * of 78 (nx + 2)(ny + 2) doubles (1-D: 78 (nx + 2)) that the handle keeps
+ * until csh_destroy.  Asynchronous.
+ */
+int csh_adjoint_step(csh_grid *h, double dt, const void *U, const void *lam_next, void *lam);
+
+/*
+ * Transpose of the primitive-to-conserved map of csh_init_state (Sec. 2:
+ * U = (rho, rho u, rho v, Pxx + rho u^2, Pxy + rho u v, Pyy + rho v^2)) at W:
+ * lam_W = (dU/dW)^T lam_U, to carry a gradient with respect to the initial
+ * conserved state back to the primitive fields (density, velocity, stress).
+ * W, lam_U: device, read; lam_W: device output; [6][ny][nx] FP64.  Asynchronous.
+ */
+int csh_init_state_adjoint(csh_grid *h, const void *W, const void *lam_U, void *lam_W);
+
+/* Release the handle (synchronises its stream first). */
+int csh_destroy(csh_grid *h);
+
+/* ---- many independent 1-D problems of uneven length, one launch ---------------------------- */
+
+/*
+ * ntubes independent 1-D tubes, tube k on cells offsets[k] .. offsets[k+1]-1
+ * of concatenated SoA arrays [6][offsets[ntubes]]; each tube spans [0, 1]
+ * (dx = 1 / its length) with outflow ends.  offsets: HOST array of ntubes + 1
+ * nondecreasing values, offsets[0] = 0, every length >= 1.
+ * W: device primitive fields, read; U: device, receives the conserved state.
+ * dtype: CSH_F64.  Synchronises; errors as csh_init_state.
+ */
+int csh_batch_init(csh_batch **b, int ntubes, const int64_t *offsets, int dtype, const void *W,
+                   void *U, void *stream);
+
+/*
+ * Advance every tube nsteps steps, each with its own CFL timestep
+ * dt = cfl / s_k recomputed on the device after every step, in one persistent
+ * launch (workgroups take whole tubes, longest first, from a device queue;
+ * replayed from a captured HIP graph).  U is updated in place (U_work: caller
+ * buffer of the same size).  dt_out: device array [ntubes][nsteps] of the
+ * timesteps taken, or NULL.  threads: workgroup size (64, 128, 256, 512 or
+ * 1024), or 0 for the size chosen by csh_batch_autotune (256 if never tuned).
+ */
+int csh_batch_run(csh_batch *b, int nsteps, double cfl, void *U, void *U_work, double *dt_out,
+                  int threads);
+
+/*
+ * Time the candidate workgroup sizes on this device for this batch (a few
+ * steps each, on scratch copies of U; U is not modified), keep the fastest
+ * as the batch's default and write it to *best_threads.  Synchronises.
+ */
+int csh_batch_autotune(csh_batch *b, int probe_steps, double cfl, const void *U, int *best_threads);
+
+int csh_batch_destroy(csh_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSHYDRO_H */

@@ -111,6 +111,7 @@ def lib():
         L.orc_limited_slope.argtypes = [ctypes.c_int, _D, _D, _D, _D]
         L.orc_trace.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, _D, _D]
         L.orc_hll.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -174,6 +175,11 @@ def hll(direction: int, wl, wr) -> np.ndarray:
     wl, wr = _vec(wl), _vec(wr); out = np.empty(6)
     lib().orc_hll(direction, _p(wl), _p(wr), _p(out))
     return out
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().orc_num_threads())
 
 
 # ---- fields ----------------------------------------------------------------------------
@@ -240,7 +246,7 @@ def physical(g: Grid, U: np.ndarray) -> bool:
 # ---- drivers ---------------------------------------------------------------------------
 
 def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
-            t_end: float | None = None, max_steps: int = 100000):
+            t_end: float | None = None, max_steps: int = 20000):
     """Advance with dt = cfl / s (s from the state at the start of each step).
 
     Stops after ``nsteps`` steps, or when ``t_end`` is reached (the last step is
@@ -256,6 +262,8 @@ def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
         if len(dts) >= max_steps:
             raise RuntimeError("too many steps")
         dt = cfl / max_signal_speed(g, U)
+        if not (dt > 0.0 and dt < float("inf")):
+            raise FloatingPointError(f"timestep {dt} at step {len(dts)}: the state is not physical")
         if t_end is not None and t + dt > t_end:
             dt = t_end - t
         U = step(g, dt, U)

@@ -54,6 +54,10 @@
 
 #include "cshoracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 enum { NV = 6 };
 enum { IR = 0, IU = 1, IV = 2, IXX = 3, IXY = 4, IYY = 5 };
 
@@ -664,4 +668,14 @@ void orc_prim_field(int64_t n, const double *U, double *W)
         orc_prim(u, w);
         for (int m = 0; m < NV; ++m) W[m * n + c] = w[m];
     }
+}
+
+/* Threads the OpenMP loops of this oracle use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -53,5 +53,6 @@ int orc_physical(const orc_grid *g, const double *U);
 /* Whole-field conversions, SoA [6][n]. */
 void orc_cons_field(int64_t n, const double *W, double *U);
 void orc_prim_field(int64_t n, const double *U, double *W);
+int orc_num_threads(void);
 
 #endif

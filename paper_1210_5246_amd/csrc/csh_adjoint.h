@@ -1,0 +1,382 @@
+// Reverse-mode pieces of the sweep (FP64): vector-Jacobian products of every
+// stage of csh_device.h, written out by hand statement by statement in reverse
+// order, and the per-cell bodies of the adjoint kernels.
+//
+// Conventions: a function foo_vjp(inputs..., ybar, xbar...) ADDS the
+// contribution of ybar to the adjoints xbar of foo's inputs.  At the kinks of
+// min/max/|.| the subgradient of one branch is taken: MC takes the centred
+// difference first, then 2|dl|, then 2|dr| (first minimal argument); the
+// tracing coefficients have zero slope where their eigenvalue is exactly 0;
+// HLL speed estimates take the first argument on ties and zero slope where
+// they are clipped at 0.  All __host__ __device__, so the tests can run them
+// on the CPU.
+#pragma once
+
+#include "csh_device.h"
+
+namespace csh {
+
+using P = Prim<double>;
+using C = Cons<double>;
+using A6 = Char<double>;
+using E = Eig<double>;
+
+CSH_HD void acc(P& a, const P& b)
+{
+    a.r += b.r; a.u += b.u; a.v += b.v; a.pxx += b.pxx; a.pxy += b.pxy; a.pyy += b.pyy;
+}
+CSH_HD P scale(double s, const P& a) { return {s * a.r, s * a.u, s * a.v, s * a.pxx, s * a.pxy, s * a.pyy}; }
+CSH_HD double dot(const P& a, const P& b)
+{
+    return a.r * b.r + a.u * b.u + a.v * b.v + a.pxx * b.pxx + a.pxy * b.pxy + a.pyy * b.pyy;
+}
+CSH_HD P zero_p() { return {0, 0, 0, 0, 0, 0}; }
+CSH_HD C zero_c() { return {0, 0, 0, 0, 0, 0}; }
+
+// eig_x(w, ir): c = sqrt(pxx ir), a = sqrt3 c, h2c = 0.5/c, h2a = k/c, ip = 1/pxx, q = pxy ip
+CSH_HD void eig_vjp(const P& w, double ir, const E& e, const E& eb, P& wb, double& irb)
+{
+    double cb = eb.c;
+    double ipb = eb.ip;
+    // q = pxy * ip
+    wb.pxy += e.ip * eb.q;
+    ipb += w.pxy * eb.q;
+    // ip = 1 / pxx
+    wb.pxx += -e.ip * e.ip * ipb;
+    // h2a = k / c ; h2c = 0.5 / c ; a = sqrt3 c
+    cb += -e.h2a / e.c * eb.h2a;
+    cb += -e.h2c / e.c * eb.h2c;
+    cb += 1.7320508075688772935 * eb.a;
+    // c = sqrt(pxx ir)
+    const double tb = cb / (2.0 * e.c);
+    wb.pxx += ir * tb;
+    irb += w.pxx * tb;
+}
+
+// project(w, e, d) -> alpha
+CSH_HD void project_vjp(const P& w, const E& e, const P& d, const A6& ab, P& wb, E& eb, P& db)
+{
+    const double t1b = ab.a1 + ab.a6, t2b = ab.a6 - ab.a1;
+    const double hb = ab.a2 - ab.a5, sb = ab.a2 + ab.a5;
+    // a3 = d.r - w.r d.pxx ip / 3
+    db.r += ab.a3;
+    wb.r += -d.pxx * e.ip / 3.0 * ab.a3;
+    db.pxx += -w.r * e.ip / 3.0 * ab.a3;
+    eb.ip += -w.r * d.pxx / 3.0 * ab.a3;
+    // a4 = d.pyy - 2 q d.pxy + (4 q^2 - pyy ip) d.pxx / 3
+    db.pyy += ab.a4;
+    eb.q += (-2.0 * d.pxy + 8.0 * e.q * d.pxx / 3.0) * ab.a4;
+    db.pxy += -2.0 * e.q * ab.a4;
+    wb.pyy += -e.ip * d.pxx / 3.0 * ab.a4;
+    eb.ip += -w.pyy * d.pxx / 3.0 * ab.a4;
+    db.pxx += (4.0 * e.q * e.q - w.pyy * e.ip) / 3.0 * ab.a4;
+    // h = (q d.u - d.v) h2c
+    const double X = e.q * d.u - d.v;
+    const double Xb = e.h2c * hb;
+    eb.h2c += X * hb;
+    eb.q += d.u * Xb;
+    db.u += e.q * Xb;
+    db.v -= Xb;
+    // s = (d.pxy - q d.pxx) (ip / 2)
+    const double Y = d.pxy - e.q * d.pxx;
+    const double Yb = 0.5 * e.ip * sb;
+    eb.ip += 0.5 * Y * sb;
+    db.pxy += Yb;
+    eb.q -= d.pxx * Yb;
+    db.pxx -= e.q * Yb;
+    // t2 = d.u h2a
+    db.u += e.h2a * t2b;
+    eb.h2a += d.u * t2b;
+    // t1 = d.pxx ip / 6
+    db.pxx += e.ip / 6.0 * t1b;
+    eb.ip += d.pxx / 6.0 * t1b;
+}
+
+// backproject(w, e, alpha) -> d
+CSH_HD void backproject_vjp(const P& w, const E& e, const A6& al, const P& db, P& wb, E& eb, A6& ab)
+{
+    const double S = al.a1 + al.a6, D = al.a6 - al.a1;
+    const double S25 = al.a2 + al.a5, D25 = al.a5 - al.a2;
+    const double Sb = w.r * db.r + 3.0 * w.pxx * db.pxx + 3.0 * w.pxy * db.pxy + (w.pyy + 2.0 * w.pxy * e.q) * db.pyy;
+    const double Db = e.a * db.u + e.a * e.q * db.v;
+    const double S25b = w.pxx * db.pxy + 2.0 * w.pxy * db.pyy;
+    const double D25b = e.c * db.v;
+    ab.a3 += db.r;
+    ab.a4 += db.pyy;
+    wb.r += S * db.r;
+    eb.a += D * db.u + e.q * D * db.v;
+    eb.q += e.a * D * db.v + 2.0 * w.pxy * S * db.pyy;
+    eb.c += D25 * db.v;
+    wb.pxx += 3.0 * S * db.pxx + S25 * db.pxy;
+    wb.pxy += 3.0 * S * db.pxy + 2.0 * e.q * S * db.pyy + 2.0 * S25 * db.pyy;
+    wb.pyy += S * db.pyy;
+    ab.a1 += Sb - Db;
+    ab.a6 += Sb + Db;
+    ab.a2 += S25b - D25b;
+    ab.a5 += S25b + D25b;
+}
+
+// MC: m = sgn(dc) min(2|dl|, |dc|, 2|dr|) if dl dr > 0, else 0
+CSH_HD void mc_vjp(double dl, double dr, double mb, double& dlb, double& drb)
+{
+    if (!(dl * dr > 0.0)) return;
+    const double dc = 0.5 * (dl + dr);
+    const double adc = fabs(dc), al2 = 2.0 * fabs(dl), ar2 = 2.0 * fabs(dr);
+    if (adc <= al2 && adc <= ar2) {  // centred difference
+        dlb += 0.5 * mb;
+        drb += 0.5 * mb;
+    } else if (al2 <= ar2) {          // 2 dl (same sign as dc)
+        dlb += 2.0 * mb;
+    } else {
+        drb += 2.0 * mb;
+    }
+}
+
+// limited_slope(w, e, dl, dr) -> dm
+CSH_HD void limited_slope_vjp(const P& w, const E& e, const P& dl, const P& dr, const P& dmb, P& wb, E& eb,
+                              P& dlb, P& drb)
+{
+    const A6 l = project(w, e, dl), r = project(w, e, dr);
+    A6 m;
+    m.a1 = mc(l.a1, r.a1);
+    m.a2 = mc(l.a2, r.a2);
+    m.a3 = mc(l.a3, r.a3);
+    m.a4 = mc(l.a4, r.a4);
+    m.a5 = mc(l.a5, r.a5);
+    m.a6 = mc(l.a6, r.a6);
+    A6 mb{0, 0, 0, 0, 0, 0};
+    backproject_vjp(w, e, m, dmb, wb, eb, mb);
+    A6 lb{0, 0, 0, 0, 0, 0}, rb{0, 0, 0, 0, 0, 0};
+    mc_vjp(l.a1, r.a1, mb.a1, lb.a1, rb.a1);
+    mc_vjp(l.a2, r.a2, mb.a2, lb.a2, rb.a2);
+    mc_vjp(l.a3, r.a3, mb.a3, lb.a3, rb.a3);
+    mc_vjp(l.a4, r.a4, mb.a4, lb.a4, rb.a4);
+    mc_vjp(l.a5, r.a5, mb.a5, lb.a5, rb.a5);
+    mc_vjp(l.a6, r.a6, mb.a6, lb.a6, rb.a6);
+    project_vjp(w, e, dl, lb, wb, eb, dlb);
+    project_vjp(w, e, dr, rb, wb, eb, drb);
+}
+
+// jac_x(w, ir, d) -> o
+CSH_HD void jac_vjp(const P& w, double ir, const P& d, const P& ob, P& wb, double& irb, P& db)
+{
+    wb.u += d.r * ob.r + d.u * ob.u + d.v * ob.v + d.pxx * ob.pxx + d.pxy * ob.pxy + d.pyy * ob.pyy;
+    wb.r += d.u * ob.r;
+    irb += d.pxx * ob.u + d.pxy * ob.v;
+    wb.pxx += 3.0 * d.u * ob.pxx + d.v * ob.pxy;
+    wb.pxy += 2.0 * d.u * ob.pxy + 2.0 * d.v * ob.pyy;
+    wb.pyy += d.u * ob.pyy;
+    db.r += w.u * ob.r;
+    db.u += w.r * ob.r + w.u * ob.u + 3.0 * w.pxx * ob.pxx + 2.0 * w.pxy * ob.pxy + w.pyy * ob.pyy;
+    db.v += w.u * ob.v + w.pxx * ob.pxy + 2.0 * w.pxy * ob.pyy;
+    db.pxx += ir * ob.u + w.u * ob.pxx;
+    db.pxy += ir * ob.v + w.u * ob.pxy;
+    db.pyy += w.u * ob.pyy;
+}
+
+CSH_HD P swapb(const P& a) { return swap(a); }  // the adjoint of a permutation that is its own inverse
+
+// face_states<TWOD>(W0, Wl, Wr, Wm, Wp, kx, ky): adjoints of the five input states
+template <bool TWOD>
+CSH_HD void face_states_vjp(const P& W0, const P& Wl, const P& Wr, const P& Wm, const P& Wp, double kx, double ky,
+                            const Faces<double>& fb, P& W0b, P& Wlb, P& Wrb, P& Wmb, P& Wpb)
+{
+    // ---- forward recompute ----
+    const double ir = 1.0 / W0.r;
+    const E ex = eig_x(W0, ir);
+    const P dlx = sub(W0, Wl), drx = sub(Wr, W0);
+    const P dxm = limited_slope(W0, ex, dlx, drx);
+    const double chix = 0.5 + kx * fmin(W0.u + ex.a, 0.0);
+    const double clox = 0.5 - kx * fmax(W0.u - ex.a, 0.0);
+    P W0s{}, dyms{}, dym{}, dlys{}, drys{};
+    E ey{};
+    double chiy = 0, cloy = 0;
+    if constexpr (TWOD) {
+        W0s = swap(W0);
+        ey = eig_x(W0s, ir);
+        dlys = swap(sub(W0, Wm));
+        drys = swap(sub(Wp, W0));
+        dyms = limited_slope(W0s, ey, dlys, drys);
+        dym = swap(dyms);
+        chiy = 0.5 + ky * fmin(W0.v + ey.a, 0.0);
+        cloy = 0.5 - ky * fmax(W0.v - ey.a, 0.0);
+    }
+    // ---- reverse ----
+    double irb = 0.0;
+    E exb{0, 0, 0, 0, 0, 0}, eyb{0, 0, 0, 0, 0, 0};
+    P baseb = zero_p(), dxmb = zero_p(), dymb = zero_p();
+    // xhi = base + chix dxm ; xlo = base - clox dxm
+    acc(baseb, fb.xhi);
+    acc(baseb, fb.xlo);
+    acc(dxmb, scale(chix, fb.xhi));
+    acc(dxmb, scale(-clox, fb.xlo));
+    const double chixb = dot(dxm, fb.xhi), cloxb = -dot(dxm, fb.xlo);
+    if constexpr (TWOD) {
+        acc(baseb, fb.yhi);
+        acc(baseb, fb.ylo);
+        acc(dymb, scale(chiy, fb.yhi));
+        acc(dymb, scale(-cloy, fb.ylo));
+        const double chiyb = dot(dym, fb.yhi), cloyb = -dot(dym, fb.ylo);
+        // chiy = 1/2 + ky min(v + ay, 0) ; cloy = 1/2 - ky max(v - ay, 0)
+        if (W0.v + ey.a < 0.0) {
+            W0b.v += ky * chiyb;
+            eyb.a += ky * chiyb;
+        }
+        if (W0.v - ey.a > 0.0) {
+            W0b.v -= ky * cloyb;
+            eyb.a += ky * cloyb;
+        }
+        // base -= ky swap(jac_x(W0s, ir, dyms))
+        P W0sb = zero_p(), dymsb = swapb(dymb);
+        jac_vjp(W0s, ir, dyms, scale(-ky, swapb(baseb)), W0sb, irb, dymsb);
+        // dyms = limited_slope(W0s, ey, dlys, drys)
+        P dlysb = zero_p(), drysb = zero_p();
+        limited_slope_vjp(W0s, ey, dlys, drys, dymsb, W0sb, eyb, dlysb, drysb);
+        eig_vjp(W0s, ir, ey, eyb, W0sb, irb);
+        acc(W0b, swapb(W0sb));
+        // dlys = swap(W0 - Wm), drys = swap(Wp - W0)
+        const P dlyb = swapb(dlysb), dryb = swapb(drysb);
+        acc(W0b, dlyb);
+        acc(Wmb, scale(-1.0, dlyb));
+        acc(Wpb, dryb);
+        acc(W0b, scale(-1.0, dryb));
+    }
+    // chix = 1/2 + kx min(u + ax, 0) ; clox = 1/2 - kx max(u - ax, 0)
+    if (W0.u + ex.a < 0.0) {
+        W0b.u += kx * chixb;
+        exb.a += kx * chixb;
+    }
+    if (W0.u - ex.a > 0.0) {
+        W0b.u -= kx * cloxb;
+        exb.a += kx * cloxb;
+    }
+    // base = W0 - kx jac_x(W0, ir, dxm) (- transverse term, done above)
+    acc(W0b, baseb);
+    jac_vjp(W0, ir, dxm, scale(-kx, baseb), W0b, irb, dxmb);
+    P dlxb = zero_p(), drxb = zero_p();
+    limited_slope_vjp(W0, ex, dlx, drx, dxmb, W0b, exb, dlxb, drxb);
+    eig_vjp(W0, ir, ex, exb, W0b, irb);
+    // dlx = W0 - Wl, drx = Wr - W0
+    acc(W0b, dlxb);
+    acc(Wlb, scale(-1.0, dlxb));
+    acc(Wrb, drxb);
+    acc(W0b, scale(-1.0, drxb));
+    // ir = 1 / W0.r
+    W0b.r += -ir * ir * irb;
+}
+
+// to_cons(w): mx = r u, my = r v, exx = pxx + mx u, exy = pxy + mx v, eyy = pyy + my v
+CSH_HD void to_cons_vjp(const P& w, const C& Ub, P& wb)
+{
+    const double mx = w.r * w.u, my = w.r * w.v;
+    wb.pxx += Ub.exx;
+    wb.pxy += Ub.exy;
+    wb.pyy += Ub.eyy;
+    const double mxb = Ub.mx + w.u * Ub.exx + w.v * Ub.exy;
+    const double myb = Ub.my + w.v * Ub.eyy;
+    wb.u += mx * Ub.exx + w.r * mxb;
+    wb.v += mx * Ub.exy + my * Ub.eyy + w.r * myb;
+    wb.r += Ub.r + w.u * mxb + w.v * myb;
+}
+
+// to_prim(U): u = mx ir, v = my ir, pxx = exx - mx u, pxy = exy - mx v, pyy = eyy - my v
+CSH_HD void to_prim_vjp(const C& U, const P& wb, C& Ub)
+{
+    const double ir = 1.0 / U.r;
+    const double u = U.mx * ir, v = U.my * ir;
+    Ub.exx += wb.pxx;
+    Ub.exy += wb.pxy;
+    Ub.eyy += wb.pyy;
+    const double ub = wb.u - U.mx * wb.pxx;
+    const double vb = wb.v - U.mx * wb.pxy - U.my * wb.pyy;
+    Ub.mx += -u * wb.pxx - v * wb.pxy + ir * ub;
+    Ub.my += -v * wb.pyy + ir * vb;
+    const double irb = U.mx * ub + U.my * vb;
+    Ub.r += wb.r - ir * ir * irb;
+}
+
+// flux_x(w, U)
+CSH_HD void flux_vjp(const P& w, const C& U, const C& Fb, P& wb, C& Ub)
+{
+    Ub.mx += Fb.r + w.u * Fb.mx;
+    Ub.my += w.u * Fb.my;
+    Ub.exx += w.u * Fb.exx;
+    Ub.exy += w.u * Fb.exy;
+    Ub.eyy += w.u * Fb.eyy;
+    wb.u += U.mx * Fb.mx + U.my * Fb.my + (U.exx + 2.0 * w.pxx) * Fb.exx + (U.exy + w.pxy) * Fb.exy + U.eyy * Fb.eyy;
+    wb.v += w.pxx * Fb.exy + 2.0 * w.pxy * Fb.eyy;
+    wb.pxx += Fb.mx + 2.0 * w.u * Fb.exx + w.v * Fb.exy;
+    wb.pxy += Fb.my + w.u * Fb.exy + 2.0 * w.v * Fb.eyy;
+}
+
+// hll_x(make_face_x(wl), make_face_x(wr)): adjoints of the two primitive face states
+CSH_HD void hll_vjp(const P& wl, const P& wr, const C& Fb, P& wlb, P& wrb)
+{
+    const Face<double> L = make_face_x(wl), R = make_face_x(wr);
+    const double A1 = L.w.u - L.a, B1 = R.w.u - R.a;
+    const double C1 = L.w.u + L.a, D1 = R.w.u + R.a;
+    const double sl = fmin(fmin(A1, B1), 0.0);
+    const double sr = fmax(fmax(C1, D1), 0.0);
+    const double inv = 1.0 / (sr - sl);
+    const double slr = sl * sr;
+    const C FL = flux_x(L.w, L.U), FR = flux_x(R.w, R.U);
+    const double fl[6] = {FL.r, FL.mx, FL.my, FL.exx, FL.exy, FL.eyy};
+    const double fr[6] = {FR.r, FR.mx, FR.my, FR.exx, FR.exy, FR.eyy};
+    const double ul[6] = {L.U.r, L.U.mx, L.U.my, L.U.exx, L.U.exy, L.U.eyy};
+    const double ur[6] = {R.U.r, R.U.mx, R.U.my, R.U.exx, R.U.exy, R.U.eyy};
+    const double fb[6] = {Fb.r, Fb.mx, Fb.my, Fb.exx, Fb.exy, Fb.eyy};
+    double flb[6], frb[6], ulb[6], urb[6];
+    double srb = 0, slb = 0, invb = 0, slrb = 0;
+    for (int k = 0; k < 6; ++k) {
+        const double du = ur[k] - ul[k];
+        const double N = sr * fl[k] - sl * fr[k] + slr * du;
+        const double Nb = inv * fb[k];
+        invb += N * fb[k];
+        flb[k] = sr * Nb;
+        frb[k] = -sl * Nb;
+        srb += fl[k] * Nb;
+        slb -= fr[k] * Nb;
+        slrb += du * Nb;
+        urb[k] = slr * Nb;
+        ulb[k] = -slr * Nb;
+    }
+    srb += sl * slrb;
+    slb += sr * slrb;
+    // inv = 1 / (sr - sl)
+    srb += -inv * inv * invb;
+    slb += inv * inv * invb;
+    double ulwb = 0, urwb = 0, alb = 0, arb = 0;  // adjoints of u_L, u_R, a_L, a_R
+    if (fmin(A1, B1) < 0.0) {
+        if (A1 <= B1) { ulwb += slb; alb -= slb; }
+        else { urwb += slb; arb -= slb; }
+    }
+    if (fmax(C1, D1) > 0.0) {
+        if (C1 >= D1) { ulwb += srb; alb += srb; }
+        else { urwb += srb; arb += srb; }
+    }
+    C ULb = {ulb[0], ulb[1], ulb[2], ulb[3], ulb[4], ulb[5]};
+    C URb = {urb[0], urb[1], urb[2], urb[3], urb[4], urb[5]};
+    flux_vjp(L.w, L.U, C{flb[0], flb[1], flb[2], flb[3], flb[4], flb[5]}, wlb, ULb);
+    flux_vjp(R.w, R.U, C{frb[0], frb[1], frb[2], frb[3], frb[4], frb[5]}, wrb, URb);
+    to_cons_vjp(L.w, ULb, wlb);
+    to_cons_vjp(R.w, URb, wrb);
+    wlb.u += ulwb;
+    wrb.u += urwb;
+    // a = sqrt(3 pxx / r)
+    wlb.pxx += L.a / (2.0 * L.w.pxx) * alb;
+    wlb.r += -L.a / (2.0 * L.w.r) * alb;
+    wrb.pxx += R.a / (2.0 * R.w.pxx) * arb;
+    wrb.r += -R.a / (2.0 * R.w.r) * arb;
+}
+
+// the fixed-field kick is affine in U with a constant Jacobian K; lam' = K^T lam
+CSH_HD C kick_vjp(const C& lb, double h, double ax, double ay)
+{
+    C o = lb;
+    o.r += h * ax * lb.mx + h * ay * lb.my + h * h * (ax * ax * lb.exx + ax * ay * lb.exy + ay * ay * lb.eyy);
+    o.mx += 2.0 * h * ax * lb.exx + h * ay * lb.exy;
+    o.my += h * ax * lb.exy + 2.0 * h * ay * lb.eyy;
+    return o;
+}
+
+}  // namespace csh

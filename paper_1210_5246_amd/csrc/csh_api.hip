@@ -1,0 +1,346 @@
+// C ABI of the sweep (declarations and contracts in include/cshydro.h).
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+
+#include "cshydro.h"
+#include "csh_api_util.h"
+#include "csh_internal.h"
+
+using csh::Slot;
+
+thread_local std::string csh_err_msg;
+
+extern "C" const char* csh_last_error(void) { return csh_err_msg.c_str(); }
+
+struct csh_grid {
+    int nx = 0, ny = 0, bcx = 0, bcy = 0, dtype = CSH_F64;
+    double dx = 1, dy = 1;
+    double vc = 0, rc = 0, x0 = 0, y0 = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // private stream used only to record graphs
+    Slot* slots = nullptr;          // 3 device slots (see csh_internal.h)
+    int* flag = nullptr;            // device: 1 once a non-physical state was seen
+    int phase = 0;                  // slot holding the rate of the latest output
+    int ty = 32;                    // rows per wavefront segment
+    double* adj_ws = nullptr;       // adjoint workspace, allocated on first use
+    size_t adj_ws_n = 0;
+    // cached graph of csh_run_cfl
+    hipGraphExec_t exec = nullptr;
+    int g_nsteps = -1;
+    double g_cfl = 0, g_tend = 0;
+    const void *g_U = nullptr, *g_W = nullptr, *g_log = nullptr;
+};
+
+namespace {
+
+int rows_per_segment(int nx, int ny)
+{
+    if (const char* e = std::getenv("CSH_ROWS")) {
+        const int v = std::atoi(e);
+        if (v >= 1) return v;
+    }
+    // aim at >= 8192 wavefronts (8 per SIMD) with segments of 4..64 rows
+    const long strips = (nx + csh::kStrip - 1) / csh::kStrip;
+    long t = (long)ny * strips / 8192;
+    int ty = 4;
+    while (ty < 64 && ty * 2 <= t) ty *= 2;
+    return ty;
+}
+
+template <typename T>
+csh::StepArgs<T> base_args(const csh_grid* h)
+{
+    csh::StepArgs<T> a{};
+    a.nx = h->nx;
+    a.ny = h->ny;
+    a.bcx = h->bcx;
+    a.bcy = h->bcy;
+    a.dx = h->dx;
+    a.dy = h->dy;
+    a.nstrips = (h->nx + csh::kStrip - 1) / csh::kStrip;
+    a.ty = h->ny > 1 ? h->ty : 1;
+    a.nsegs = (h->ny + a.ty - 1) / a.ty;
+    a.slots = h->slots;
+    a.vc2 = h->vc * h->vc;
+    a.rc2 = h->rc * h->rc;
+    a.x0 = h->x0;
+    a.y0 = h->y0;
+    a.flag = h->flag;
+    return a;
+}
+
+template <typename T>
+hipError_t enqueue_step(csh_grid* h, const void* U, void* Un, int dev_dt, double dt, double cfl,
+                        double t_end, double* dt_log, hipStream_t s)
+{
+    auto a = base_args<T>(h);
+    a.U = static_cast<const T*>(U);
+    a.Unew = static_cast<T*>(Un);
+    a.dev_dt = dev_dt;
+    a.dt = dt;
+    a.cfl = cfl;
+    a.t_end = t_end;
+    a.dt_log = dt_log;
+    a.s_in = h->phase;
+    a.s_out = (h->phase + 1) % 3;
+    a.s_reset = (h->phase + 2) % 3;
+    h->phase = a.s_out;
+    return csh::launch_step<T>(a, h->ny > 1, false, s);
+}
+
+hipError_t enqueue_maxspeed(csh_grid* h, const void* U, hipStream_t s)
+{
+    hipError_t e = csh::launch_reset(h->slots, 3, 0.0, s);
+    if (e != hipSuccess) return e;
+    if (h->dtype == CSH_F64)
+        return csh::launch_maxspeed<double>(static_cast<const double*>(U), h->nx, h->ny, h->dx, h->dy,
+                                            h->slots + h->phase, h->flag, s);
+    return csh::launch_maxspeed<float>(static_cast<const float*>(U), h->nx, h->ny, h->dx, h->dy,
+                                       h->slots + h->phase, h->flag, s);
+}
+
+int read_rate(csh_grid* h, double* s)
+{
+    Slot sl;
+    int flag = 0;
+    CSH_HIP(hipMemcpyAsync(&sl, h->slots + h->phase, sizeof(Slot), hipMemcpyDeviceToHost, h->stream));
+    CSH_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    CSH_HIP(hipStreamSynchronize(h->stream));
+    union {
+        unsigned long long u;
+        double d;
+    } c;
+    c.u = sl.s_bits;
+    *s = c.d;
+    if (flag) return csh_fail(CSH_ERR_NONPHYSICAL, "non-physical state (rho <= 0, stress not positive-definite or non-finite)");
+    return CSH_OK;
+}
+
+void drop_graph(csh_grid* h)
+{
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    h->exec = nullptr;
+    h->g_nsteps = -1;
+}
+
+}  // namespace
+
+int csh_fail(int code, const std::string& msg)
+{
+    csh_err_msg = msg;
+    return code;
+}
+
+extern "C" int csh_init_state(csh_grid** out, int nx, int ny, double dx, double dy, int bc_x, int bc_y,
+                              int dtype, const void* W, void* U, void* stream)
+{
+    if (!out) return csh_fail(CSH_ERR_ARG, "h is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1) return csh_fail(CSH_ERR_ARG, "nx and ny must be >= 1");
+    if ((long long)nx * ny > (1LL << 31)) return csh_fail(CSH_ERR_ARG, "grid larger than 2^31 cells");
+    if (!(dx > 0) || (ny > 1 && !(dy > 0))) return csh_fail(CSH_ERR_ARG, "dx, dy must be > 0");
+    if ((bc_x != CSH_BC_PERIODIC && bc_x != CSH_BC_OUTFLOW) || (bc_y != CSH_BC_PERIODIC && bc_y != CSH_BC_OUTFLOW))
+        return csh_fail(CSH_ERR_ARG, "bad boundary condition");
+    if (dtype != CSH_F64 && dtype != CSH_F32) return csh_fail(CSH_ERR_ARG, "bad dtype");
+    if (!W || !U) return csh_fail(CSH_ERR_ARG, "W and U must be device pointers");
+    csh_grid* h = new csh_grid;
+    h->nx = nx;
+    h->ny = ny;
+    h->dx = dx;
+    h->dy = ny > 1 ? dy : 1.0;
+    h->bcx = bc_x;
+    h->bcy = bc_y;
+    h->dtype = dtype;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->ty = rows_per_segment(nx, ny);
+    auto cleanup = [&](int code) {
+        csh_destroy(h);
+        return code;
+    };
+    if (hipMalloc(&h->slots, 3 * sizeof(Slot)) != hipSuccess || hipMalloc(&h->flag, sizeof(int)) != hipSuccess)
+        return cleanup(csh_fail(CSH_ERR_HIP, "hipMalloc of the handle's scalars failed"));
+    if (hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(csh_fail(CSH_ERR_HIP, "hipStreamCreate failed"));
+    const int64_t n = (int64_t)nx * ny;
+    hipError_t e = csh::launch_reset(h->slots, 3, 0.0, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int), h->stream);
+    if (e == hipSuccess)
+        e = dtype == CSH_F64 ? csh::launch_init<double>(static_cast<const double*>(W), static_cast<double*>(U), n, h->flag, h->stream)
+                             : csh::launch_init<float>(static_cast<const float*>(W), static_cast<float*>(U), n, h->flag, h->stream);
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return cleanup(csh_fail(CSH_ERR_HIP, std::string("init: ") + hipGetErrorString(e)));
+    *out = h;
+    if (flag) return csh_fail(CSH_ERR_NONPHYSICAL, "initial state not physical");
+    return CSH_OK;
+}
+
+extern "C" int csh_set_potential(csh_grid* h, double vc, double rc, double x0, double y0)
+{
+    if (!h) return csh_fail(CSH_ERR_ARG, "h is NULL");
+    if (vc != 0 && !(rc > 0)) return csh_fail(CSH_ERR_ARG, "rc must be > 0");
+    h->vc = vc;
+    h->rc = rc;
+    h->x0 = x0;
+    h->y0 = y0;
+    drop_graph(h);
+    return CSH_OK;
+}
+
+extern "C" int csh_step(csh_grid* h, double dt, const void* U, void* U_new)
+{
+    if (!h || !U || !U_new) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (U == U_new) return csh_fail(CSH_ERR_ARG, "U and U_new must be distinct buffers");
+    if (!(dt >= 0)) return csh_fail(CSH_ERR_ARG, "dt must be >= 0");
+    hipError_t e = h->dtype == CSH_F64 ? enqueue_step<double>(h, U, U_new, 0, dt, 0, 0, nullptr, h->stream)
+                                       : enqueue_step<float>(h, U, U_new, 0, dt, 0, 0, nullptr, h->stream);
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("step: ") + hipGetErrorString(e));
+    return CSH_OK;
+}
+
+extern "C" int csh_max_signal_speed(csh_grid* h, const void* U, double* s)
+{
+    if (!h || !U || !s) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    hipError_t e = enqueue_maxspeed(h, U, h->stream);
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("max_signal_speed: ") + hipGetErrorString(e));
+    return read_rate(h, s);
+}
+
+extern "C" int csh_last_signal_speed(csh_grid* h, double* s)
+{
+    if (!h || !s) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    return read_rate(h, s);
+}
+
+extern "C" int csh_fluxes(csh_grid* h, double dt, const void* U, void* Fx, void* Fy)
+{
+    if (!h || !U || !Fx || (h->ny > 1 && !Fy)) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    hipError_t e;
+    if (h->dtype == CSH_F64) {
+        auto a = base_args<double>(h);
+        a.U = static_cast<const double*>(U);
+        a.Fx = static_cast<double*>(Fx);
+        a.Fy = static_cast<double*>(Fy);
+        a.dt = dt;
+        a.s_in = h->phase;
+        e = csh::launch_step<double>(a, h->ny > 1, true, h->stream);
+    } else {
+        auto a = base_args<float>(h);
+        a.U = static_cast<const float*>(U);
+        a.Fx = static_cast<float*>(Fx);
+        a.Fy = static_cast<float*>(Fy);
+        a.dt = dt;
+        a.s_in = h->phase;
+        e = csh::launch_step<float>(a, h->ny > 1, true, h->stream);
+    }
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("fluxes: ") + hipGetErrorString(e));
+    return CSH_OK;
+}
+
+namespace {
+
+hipError_t enqueue_run(csh_grid* h, int nsteps, double cfl, double t_end, void* U, void* Uw, double* dt_log,
+                       hipStream_t s)
+{
+    h->phase = 0;
+    hipError_t e = enqueue_maxspeed(h, U, s);  // rate of the initial state into slot 0, t = 0
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+        void* in = (k % 2 == 0) ? U : Uw;
+        void* outp = (k % 2 == 0) ? Uw : U;
+        double* lg = dt_log ? dt_log + k : nullptr;
+        e = h->dtype == CSH_F64 ? enqueue_step<double>(h, in, outp, 1, 0, cfl, t_end, lg, s)
+                                : enqueue_step<float>(h, in, outp, 1, 0, cfl, t_end, lg, s);
+    }
+    if (e == hipSuccess && nsteps % 2 == 1) {
+        const int64_t n = 6LL * h->nx * h->ny;
+        e = h->dtype == CSH_F64 ? csh::launch_copy<double>(static_cast<double*>(Uw), static_cast<double*>(U), n, s)
+                                : csh::launch_copy<float>(static_cast<float*>(Uw), static_cast<float*>(U), n, s);
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" int csh_run_cfl(csh_grid* h, int nsteps, double cfl, double t_end, void* U, void* U_work,
+                           double* dt_log)
+{
+    if (!h || !U || !U_work) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (U == U_work) return csh_fail(CSH_ERR_ARG, "U and U_work must be distinct");
+    if (nsteps < 0 || !(cfl > 0)) return csh_fail(CSH_ERR_ARG, "nsteps >= 0 and cfl > 0 required");
+    if (nsteps == 0) return CSH_OK;
+    const bool same = h->exec && h->g_nsteps == nsteps && h->g_cfl == cfl && h->g_tend == t_end &&
+                      h->g_U == U && h->g_W == U_work && h->g_log == dt_log;
+    if (!same) {
+        drop_graph(h);
+        hipGraph_t g = nullptr;
+        CSH_HIP(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_run(h, nsteps, cfl, t_end, U, U_work, dt_log, h->capture);
+        hipError_t e2 = hipStreamEndCapture(h->capture, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return csh_fail(CSH_ERR_HIP, std::string("run_cfl capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            h->exec = nullptr;
+            return csh_fail(CSH_ERR_HIP, std::string("run_cfl instantiate: ") + hipGetErrorString(e));
+        }
+        h->g_nsteps = nsteps;
+        h->g_cfl = cfl;
+        h->g_tend = t_end;
+        h->g_U = U;
+        h->g_W = U_work;
+        h->g_log = dt_log;
+    }
+    CSH_HIP(hipGraphLaunch(h->exec, h->stream));
+    h->phase = nsteps % 3;
+    return CSH_OK;
+}
+
+extern "C" int csh_destroy(csh_grid* h)
+{
+    if (!h) return CSH_OK;
+    if (h->stream || h->slots) (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+    if (h->slots) (void)hipFree(h->slots);
+    if (h->flag) (void)hipFree(h->flag);
+    if (h->adj_ws) (void)hipFree(h->adj_ws);
+    delete h;
+    return CSH_OK;
+}
+
+// adjoint entry points: implemented with the adjoint kernels
+size_t csh_adjoint_workspace_doubles(int nx, int ny);
+int csh_adjoint_impl(csh_grid_view v, double dt, const void* U, const void* lam_next, void* lam, double* ws,
+                     hipStream_t s);
+int csh_init_adjoint_impl(int64_t n, const void* W, const void* lamU, void* lamW, hipStream_t s);
+
+extern "C" int csh_adjoint_step(csh_grid* h, double dt, const void* U, const void* lam_next, void* lam)
+{
+    if (!h || !U || !lam_next || !lam) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (h->dtype != CSH_F64) return csh_fail(CSH_ERR_ARG, "the adjoint is FP64 only");
+    if (lam == lam_next || lam == U) return csh_fail(CSH_ERR_ARG, "lam must not alias U or lam_next");
+    if (!(dt >= 0)) return csh_fail(CSH_ERR_ARG, "dt must be >= 0");
+    const size_t need = csh_adjoint_workspace_doubles(h->nx, h->ny);
+    if (h->adj_ws_n < need) {
+        CSH_HIP(hipStreamSynchronize(h->stream));
+        if (h->adj_ws) (void)hipFree(h->adj_ws);
+        h->adj_ws = nullptr;
+        h->adj_ws_n = 0;
+        CSH_HIP(hipMalloc(&h->adj_ws, need * sizeof(double)));
+        h->adj_ws_n = need;
+    }
+    csh_grid_view v{h->nx, h->ny, h->bcx, h->bcy, h->dx, h->dy, h->vc, h->rc, h->x0, h->y0};
+    return csh_adjoint_impl(v, dt, U, lam_next, lam, h->adj_ws, h->stream);
+}
+
+extern "C" int csh_init_state_adjoint(csh_grid* h, const void* W, const void* lam_U, void* lam_W)
+{
+    if (!h || !W || !lam_U || !lam_W) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (h->dtype != CSH_F64) return csh_fail(CSH_ERR_ARG, "the adjoint is FP64 only");
+    return csh_init_adjoint_impl((int64_t)h->nx * h->ny, W, lam_U, lam_W, h->stream);
+}

@@ -1,0 +1,400 @@
+// Device arithmetic of the collisionless-stellar-hydrodynamics sweep
+// (Mitchell, Vorobyov & Hensler, arXiv:1210.5246), gfx950.
+//
+// Formulation used on the GPU (the scheme is the paper's; the arithmetic is
+// arranged for registers):
+//  * the eigenvectors of Sec. 3.3, eqs. (14)-(18), extended to the full
+//    symmetric 2-D stress tensor, are never stored: the projections on the
+//    left eigenvectors and the back-projection on the right ones are written
+//    out in closed form from their sparsity (about 14 FMAs each);
+//  * the characteristic tracing of eqs. (27)-(32) with the HLL terms added
+//    counts every wave once, and its per-wave sums collapse through
+//    sum_a lam_a (l_a.dw) r_a = A dw to
+//        w_hi = w + [1/2 + k min(lamM, 0)] dw - k A dw
+//        w_lo = w - [1/2 - k max(lam0, 0)] dw - k A dw ,
+//    with A the sparse primitive Jacobian;
+//  * with the transverse predictor of the unsplit scheme, all four face
+//    states of a cell share one centre value
+//        base = w - (dt/2dx) A dw_x - (dt/2dy) B dw_y ;
+//  * HLL (Davis speeds) in the branch-free form with S_L' = min(S_L, 0) and
+//    S_R' = max(S_R, 0), which equals the three-case formula.
+// Variables: primitive W = (rho, u, v, Pxx, Pxy, Pyy), conserved
+// U = (rho, rho u, rho v, Exx, Exy, Eyy), E_ij = P_ij + rho u_i u_j (Sec. 2).
+// The y direction is the x direction applied to the state with the axes
+// exchanged (swap()).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+// host-and-device arithmetic (also exercised on the CPU by the tests)
+#define CSH_HD __host__ __device__ __forceinline__
+
+namespace csh {
+
+template <typename T>
+struct Prim {
+    T r, u, v, pxx, pxy, pyy;
+};
+
+template <typename T>
+struct Cons {
+    T r, mx, my, exx, exy, eyy;
+};
+
+// characteristic amplitudes of the waves (u-a, u-c, u[rho], u[Pyy], u+c, u+a)
+template <typename T>
+struct Char {
+    T a1, a2, a3, a4, a5, a6;
+};
+
+template <typename T>
+CSH_HD Prim<T> swap(const Prim<T>& w)
+{
+    return {w.r, w.v, w.u, w.pyy, w.pxy, w.pxx};
+}
+
+template <typename T>
+CSH_HD Cons<T> swap(const Cons<T>& U)
+{
+    return {U.r, U.my, U.mx, U.eyy, U.exy, U.exx};
+}
+
+template <typename T>
+CSH_HD Prim<T> sub(const Prim<T>& a, const Prim<T>& b)
+{
+    return {a.r - b.r, a.u - b.u, a.v - b.v, a.pxx - b.pxx, a.pxy - b.pxy, a.pyy - b.pyy};
+}
+
+// Sec. 2: E_ij = P_ij + rho u_i u_j
+template <typename T>
+CSH_HD Prim<T> to_prim(const Cons<T>& U)
+{
+    const T ir = T(1) / U.r;
+    const T u = U.mx * ir, v = U.my * ir;
+    return {U.r, u, v, U.exx - U.mx * u, U.exy - U.mx * v, U.eyy - U.my * v};
+}
+
+template <typename T>
+CSH_HD Cons<T> to_cons(const Prim<T>& w)
+{
+    const T mx = w.r * w.u, my = w.r * w.v;
+    return {w.r, mx, my, w.pxx + mx * w.u, w.pxy + mx * w.v, w.pyy + my * w.v};
+}
+
+// x flux of eqs. (2)-(4) (k = x terms), from the primitive state and its
+// conserved form: (rho u, rho u u + Pxx, rho v u + Pxy, (Exx + 2 Pxx) u,
+// (Exy + Pxy) u + Pxx v, Eyy u + 2 Pxy v)
+template <typename T>
+CSH_HD Cons<T> flux_x(const Prim<T>& w, const Cons<T>& U)
+{
+    return {U.mx,
+            U.mx * w.u + w.pxx,
+            U.my * w.u + w.pxy,
+            (U.exx + T(2) * w.pxx) * w.u,
+            (U.exy + w.pxy) * w.u + w.pxx * w.v,
+            U.eyy * w.u + T(2) * w.pxy * w.v};
+}
+
+// Per-cell coefficients of the x-direction eigen-system (eqs. (14)-(18),
+// full tensor): fast speed a = sqrt(3 Pxx / rho) (eq. (15), gamma = 3),
+// shear speed c = sqrt(Pxx / rho), q = Pxy / Pxx.
+template <typename T>
+struct Eig {
+    T a, c, h2a, h2c, ip, q;  // h2a = 1/(2a), h2c = 1/(2c), ip = 1/Pxx
+};
+
+template <typename T>
+CSH_HD Eig<T> eig_x(const Prim<T>& w, T ir)
+{
+    Eig<T> e;
+    e.c = sqrt(w.pxx * ir);
+    e.a = T(1.7320508075688772935) * e.c;  // sqrt(3) c
+    e.h2c = T(0.5) / e.c;
+    e.h2a = T(0.28867513459481288225) / e.c;  // 1 / (2 sqrt(3) c)
+    e.ip = T(1) / w.pxx;
+    e.q = w.pxy * e.ip;
+    return e;
+}
+
+// alpha = L d: amplitudes of a primitive difference on the six waves.
+template <typename T>
+CSH_HD Char<T> project(const Prim<T>& w, const Eig<T>& e, const Prim<T>& d)
+{
+    const T t1 = d.pxx * e.ip * T(1.0 / 6.0);
+    const T t2 = d.u * e.h2a;
+    const T s = (d.pxy - e.q * d.pxx) * (T(0.5) * e.ip);
+    const T h = (e.q * d.u - d.v) * e.h2c;
+    Char<T> al;
+    al.a1 = t1 - t2;
+    al.a6 = t1 + t2;
+    al.a2 = h + s;
+    al.a5 = s - h;
+    al.a3 = d.r - w.r * d.pxx * e.ip * T(1.0 / 3.0);
+    al.a4 = d.pyy - T(2) * e.q * d.pxy + (T(4) * e.q * e.q - w.pyy * e.ip) * d.pxx * T(1.0 / 3.0);
+    return al;
+}
+
+// d = R alpha: back-projection on the right eigenvectors.
+template <typename T>
+CSH_HD Prim<T> backproject(const Prim<T>& w, const Eig<T>& e, const Char<T>& al)
+{
+    const T S = al.a1 + al.a6, D = al.a6 - al.a1;
+    const T S25 = al.a2 + al.a5, D25 = al.a5 - al.a2;
+    Prim<T> d;
+    d.r = w.r * S + al.a3;
+    d.u = e.a * D;
+    d.v = e.a * e.q * D + e.c * D25;
+    d.pxx = T(3) * w.pxx * S;
+    d.pxy = T(3) * w.pxy * S + w.pxx * S25;
+    d.pyy = (w.pyy + T(2) * w.pxy * e.q) * S + T(2) * w.pxy * S25 + al.a4;
+    return d;
+}
+
+// Monotonised-central limiter, eq. (25), zero at extrema (the TVD clause).
+// With dl * dr > 0 the centred difference has the sign of both.
+template <typename T>
+CSH_HD T mc(T dl, T dr)
+{
+    const T dc = T(0.5) * (dl + dr);
+    const T m = fmin(fmin(T(2) * fabs(dl), fabs(dc)), T(2) * fabs(dr));
+    return (dl * dr > T(0)) ? copysign(m, dc) : T(0);
+}
+
+// Limited primitive slope along x: eqs. (19)-(26) with dl = w_i - w_{i-1},
+// dr = w_{i+1} - w_i; the centred amplitudes are the mean of the one-sided ones.
+template <typename T>
+CSH_HD Prim<T> limited_slope(const Prim<T>& w, const Eig<T>& e, const Prim<T>& dl,
+                                                 const Prim<T>& dr)
+{
+    const Char<T> l = project(w, e, dl), r = project(w, e, dr);
+    Char<T> m;
+    m.a1 = mc(l.a1, r.a1);
+    m.a2 = mc(l.a2, r.a2);
+    m.a3 = mc(l.a3, r.a3);
+    m.a4 = mc(l.a4, r.a4);
+    m.a5 = mc(l.a5, r.a5);
+    m.a6 = mc(l.a6, r.a6);
+    return backproject(w, e, m);
+}
+
+// A d with A the primitive x Jacobian (rows: u d_rho + rho d_u, u d_u + d_Pxx/rho,
+// u d_v + d_Pxy/rho, u d_Pxx + 3 Pxx d_u, u d_Pxy + 2 Pxy d_u + Pxx d_v,
+// u d_Pyy + Pyy d_u + 2 Pxy d_v).
+template <typename T>
+CSH_HD Prim<T> jac_x(const Prim<T>& w, T ir, const Prim<T>& d)
+{
+    Prim<T> o;
+    o.r = w.u * d.r + w.r * d.u;
+    o.u = w.u * d.u + ir * d.pxx;
+    o.v = w.u * d.v + ir * d.pxy;
+    o.pxx = w.u * d.pxx + T(3) * w.pxx * d.u;
+    o.pxy = w.u * d.pxy + T(2) * w.pxy * d.u + w.pxx * d.v;
+    o.pyy = w.u * d.pyy + w.pyy * d.u + T(2) * w.pxy * d.v;
+    return o;
+}
+
+template <typename T>
+CSH_HD Prim<T> axpy(T a, const Prim<T>& x, const Prim<T>& y)
+{
+    return {y.r + a * x.r, y.u + a * x.u, y.v + a * x.v, y.pxx + a * x.pxx, y.pxy + a * x.pxy,
+            y.pyy + a * x.pyy};
+}
+
+// A face state with the quantities its Riemann problem needs.
+template <typename T>
+struct Face {
+    Prim<T> w;
+    Cons<T> U;
+    T a;  // normal fast speed sqrt(3 Pnn / rho)
+};
+
+// x-face state from a primitive state (normal direction x)
+template <typename T>
+CSH_HD Face<T> make_face_x(const Prim<T>& w)
+{
+    Face<T> f;
+    f.w = w;
+    f.U = to_cons(w);
+    f.a = sqrt(T(3) * w.pxx / w.r);
+    return f;
+}
+
+// HLL flux in x (Davis speed estimates), branch-free form.
+template <typename T>
+CSH_HD Cons<T> hll_x(const Face<T>& L, const Face<T>& R)
+{
+    const T sl = fmin(fmin(L.w.u - L.a, R.w.u - R.a), T(0));
+    const T sr = fmax(fmax(L.w.u + L.a, R.w.u + R.a), T(0));
+    const T inv = T(1) / (sr - sl);
+    const T slr = sl * sr;
+    const Cons<T> FL = flux_x(L.w, L.U), FR = flux_x(R.w, R.U);
+    Cons<T> F;
+    F.r = (sr * FL.r - sl * FR.r + slr * (R.U.r - L.U.r)) * inv;
+    F.mx = (sr * FL.mx - sl * FR.mx + slr * (R.U.mx - L.U.mx)) * inv;
+    F.my = (sr * FL.my - sl * FR.my + slr * (R.U.my - L.U.my)) * inv;
+    F.exx = (sr * FL.exx - sl * FR.exx + slr * (R.U.exx - L.U.exx)) * inv;
+    F.exy = (sr * FL.exy - sl * FR.exy + slr * (R.U.exy - L.U.exy)) * inv;
+    F.eyy = (sr * FL.eyy - sl * FR.eyy + slr * (R.U.eyy - L.U.eyy)) * inv;
+    return F;
+}
+
+template <typename T>
+CSH_HD Face<T> swap(const Face<T>& f)
+{
+    return {swap(f.w), swap(f.U), f.a};
+}
+
+// The four time-centred face states of a cell (primitive, axes not exchanged)
+// from the cell and its four neighbours: limited slopes in x and y, and the
+// Hancock predictor with the tracing coefficients of eqs. (27)-(32) and the
+// transverse terms.  1-D: only xhi / xlo, no y terms.
+template <typename T>
+struct Faces {
+    Prim<T> xhi, xlo, yhi, ylo;
+};
+
+template <typename T, bool TWOD>
+CSH_HD Faces<T> face_states(const Prim<T>& W0, const Prim<T>& Wl, const Prim<T>& Wr, const Prim<T>& Wm,
+                            const Prim<T>& Wp, T kx, T ky)
+{
+    const T ir = T(1) / W0.r;
+    const Eig<T> ex = eig_x(W0, ir);
+    const Prim<T> dxm = limited_slope(W0, ex, sub(W0, Wl), sub(Wr, W0));
+    Prim<T> base = axpy(-kx, jac_x(W0, ir, dxm), W0);
+    Faces<T> f;
+    const T chix = T(0.5) + kx * fmin(W0.u + ex.a, T(0));
+    const T clox = T(0.5) - kx * fmax(W0.u - ex.a, T(0));
+    if constexpr (TWOD) {
+        const Prim<T> W0s = swap(W0);
+        const Eig<T> ey = eig_x(W0s, ir);
+        const Prim<T> dyms = limited_slope(W0s, ey, swap(sub(W0, Wm)), swap(sub(Wp, W0)));
+        base = axpy(-ky, swap(jac_x(W0s, ir, dyms)), base);
+        const Prim<T> dym = swap(dyms);
+        const T chiy = T(0.5) + ky * fmin(W0.v + ey.a, T(0));
+        const T cloy = T(0.5) - ky * fmax(W0.v - ey.a, T(0));
+        f.yhi = axpy(chiy, dym, base);
+        f.ylo = axpy(-cloy, dym, base);
+    }
+    f.xhi = axpy(chix, dxm, base);
+    f.xlo = axpy(-clox, dxm, base);
+    return f;
+}
+
+// CFL rate of a cell (the timestep is C / max over cells of this):
+// (|u| + a_x)/dx + (|v| + a_y)/dy, 1-D: (|u| + a_x)/dx.
+template <typename T, bool TWOD>
+CSH_HD double signal_rate(const Prim<T>& w, double idx, double idy)
+{
+    const double ir = 1.0 / double(w.r);
+    double s = (fabs(double(w.u)) + sqrt(3.0 * double(w.pxx) * ir)) * idx;
+    if (TWOD) s += (fabs(double(w.v)) + sqrt(3.0 * double(w.pyy) * ir)) * idy;
+    return s;
+}
+
+// rho > 0, positive-definite stress, everything finite
+template <typename T>
+CSH_HD bool physical(const Prim<T>& w)
+{
+    const bool pd = w.r > T(0) && w.pxx > T(0) && w.pyy > T(0) && w.pxx * w.pyy - w.pxy * w.pxy > T(0);
+    const bool fin = isfinite(w.r) && isfinite(w.u) && isfinite(w.v) && isfinite(w.pxx) &&
+                     isfinite(w.pxy) && isfinite(w.pyy);
+    return pd && fin;
+}
+
+// ---- wavefront primitives --------------------------------------------------------------------
+
+// value held by lane (lane + delta), delta = +-1; the two edge lanes receive the
+// opposite edge's value, which the callers never use (edge lanes are halo)
+__device__ __forceinline__ double lane_shift(double x, int delta)
+{
+    return __shfl(x, (int)(threadIdx.x & 63) + delta, 64);
+}
+__device__ __forceinline__ float lane_shift(float x, int delta)
+{
+    return __shfl(x, (int)(threadIdx.x & 63) + delta, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ Prim<T> lane_shift(const Prim<T>& w, int d)
+{
+    return {lane_shift(w.r, d), lane_shift(w.u, d), lane_shift(w.v, d),
+            lane_shift(w.pxx, d), lane_shift(w.pxy, d), lane_shift(w.pyy, d)};
+}
+
+template <typename T>
+__device__ __forceinline__ Cons<T> lane_shift(const Cons<T>& U, int d)
+{
+    return {lane_shift(U.r, d), lane_shift(U.mx, d), lane_shift(U.my, d),
+            lane_shift(U.exx, d), lane_shift(U.exy, d), lane_shift(U.eyy, d)};
+}
+
+template <typename T>
+__device__ __forceinline__ Face<T> lane_shift(const Face<T>& f, int d)
+{
+    return {lane_shift(f.w, d), lane_shift(f.U, d), lane_shift(f.a, d)};
+}
+
+// max over the wavefront
+__device__ __forceinline__ double wave_max(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// positive doubles order like their bit patterns
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double x)
+{
+    atomicMax(slot, (unsigned long long)__double_as_longlong(x));
+}
+
+// ---- one-dimensional sweep of a wavefront's 64 cells ------------------------------------------
+
+// HLL flux through the high face (c + 1/2) of the lane's cell c, from the
+// conserved states of the 64 consecutive cells the wavefront holds: slopes,
+// characteristic limiting, tracing (eqs. (19)-(32)), HLL.  Valid on lanes
+// 1..61 (the two edge lanes on each side lack a neighbour's slope).
+template <typename T>
+__device__ __forceinline__ Cons<T> flux_1d(const Cons<T>& U0, T kx)
+{
+    const Prim<T> W0 = to_prim(U0);
+    const Faces<T> f = face_states<T, false>(W0, lane_shift(W0, -1), lane_shift(W0, +1), W0, W0, kx, T(0));
+    return hll_x(make_face_x(f.xhi), lane_shift(make_face_x(f.xlo), +1));
+}
+
+template <typename T>
+CSH_HD Cons<T> update(const Cons<T>& U, T c, const Cons<T>& Fp, const Cons<T>& Fm)
+{
+    return {U.r - c * (Fp.r - Fm.r),       U.mx - c * (Fp.mx - Fm.mx),
+            U.my - c * (Fp.my - Fm.my),    U.exx - c * (Fp.exx - Fm.exx),
+            U.exy - c * (Fp.exy - Fm.exy), U.eyy - c * (Fp.eyy - Fm.eyy)};
+}
+
+// ---- state access ------------------------------------------------------------------------------
+
+template <typename T>
+CSH_HD Cons<T> load_cons(const T* __restrict__ U, size_t plane, size_t c)
+{
+    return {U[c], U[plane + c], U[2 * plane + c], U[3 * plane + c], U[4 * plane + c], U[5 * plane + c]};
+}
+
+template <typename T>
+CSH_HD void store_cons(T* __restrict__ U, size_t plane, size_t c, const Cons<T>& v)
+{
+    U[c] = v.r;
+    U[plane + c] = v.mx;
+    U[2 * plane + c] = v.my;
+    U[3 * plane + c] = v.exx;
+    U[4 * plane + c] = v.exy;
+    U[5 * plane + c] = v.eyy;
+}
+
+CSH_HD int map_index(int i, int n, int bc)
+{
+    if (bc == 0) {  // periodic
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);  // zero-gradient outflow
+}
+
+}  // namespace csh

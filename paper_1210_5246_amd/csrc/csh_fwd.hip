@@ -1,0 +1,280 @@
+// Forward sweep kernels of the collisionless-stellar-hydrodynamics scheme
+// (Mitchell, Vorobyov & Hensler, arXiv:1210.5246, Sec. 3.3), gfx950.
+//
+// One sweep = MUSCL-Hancock with characteristic tracing (eqs. (19)-(32)), an
+// HLL flux at every face, the dimensionally unsplit conservative update, the
+// operator-split external-gravity kick (Sec. 3.3, last paragraph) and the
+// fused reduction of the CFL rate of the new state.
+//
+// Work decomposition (2-D): one wavefront owns a strip of 60 output columns
+// and marches up a segment of rows.  Lane l holds column x0 - 2 + l, so the
+// two lanes at each edge are the stencil halo.  x neighbours come from lane
+// shuffles; the rows r-1, r, r+1 the y slopes need, the flux of the previous
+// row and the high y-face state of the cell below stay in registers.  No LDS
+// and no second pass: each input cell is read from HBM once per strip it
+// belongs to (64/60 columns) and each output cell is written once.
+#include "csh_device.h"
+#include "csh_internal.h"
+
+namespace csh {
+
+template <typename T>
+__device__ __forceinline__ double step_dt(const StepArgs<T>& p, double* t_now)
+{
+    const Slot& sl = p.slots[p.s_in];
+    const double t = sl.t;
+    *t_now = t;
+    if (!p.dev_dt) return p.dt;
+    const double s = __longlong_as_double((long long)sl.s_bits);
+    double dt = p.cfl / s;
+    if (p.t_end > 0.0) {
+        if (t >= p.t_end) dt = 0.0;
+        else if (t + dt > p.t_end) dt = p.t_end - t;
+    }
+    return dt;
+}
+
+// Exact kick of the velocity by dt * a for a fixed field a (rho and the stress
+// unchanged): rho u_i += dt rho a_i, E_ij += dt (a_i m_j + m_i a_j) + dt^2 rho a_i a_j.
+template <typename T>
+__device__ __forceinline__ void kick(Cons<T>& U, const StepArgs<T>& p, double dt, int i, int j, bool twod)
+{
+    if (p.vc2 == 0.0) return;
+    const double x = p.x0 + (i + 0.5) * p.dx;
+    const double y = twod ? p.y0 + (j + 0.5) * p.dy : 0.0;
+    const double f = -p.vc2 / (x * x + y * y + p.rc2);
+    const T ax = T(f * x), ay = T(f * y);
+    const T h = T(dt);
+    const T mx = U.mx, my = U.my;
+    U.mx = mx + h * U.r * ax;
+    U.my = my + h * U.r * ay;
+    U.exx = U.exx + h * ax * (T(2) * mx + h * U.r * ax);
+    U.exy = U.exy + h * (ax * my + mx * ay + h * U.r * ax * ay);
+    U.eyy = U.eyy + h * ay * (T(2) * my + h * U.r * ay);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_face(T* __restrict__ F, size_t plane, size_t idx, const Cons<T>& f)
+{
+    store_cons(F, plane, idx, f);
+}
+
+template <typename T, bool TWOD, bool FLUXES>
+__global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
+{
+    double t_now;
+    const double dt = step_dt(p, &t_now);
+    if (!FLUXES && blockIdx.x == 0 && threadIdx.x == 0) {
+        p.slots[p.s_out].t = t_now + dt;
+        p.slots[p.s_reset].s_bits = 0ull;
+        if (p.dt_log) *p.dt_log = dt;
+    }
+
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
+    if (wid >= p.nstrips * p.nsegs) return;  // uniform per wavefront
+    const int sx = wid % p.nstrips, sy = wid / p.nstrips;
+    const int c = sx * kStrip - 2 + lane;  // column of this lane
+    const int gc = map_index(c, p.nx, p.bcx);
+    const bool own = lane >= 2 && lane < 2 + kStrip && c < p.nx;  // lane owns an output column
+    const size_t plane = (size_t)p.nx * p.ny;
+
+    const T kx = T(dt / (2.0 * p.dx)), cx = T(dt / p.dx);
+    const double idx = 1.0 / p.dx, idy = TWOD ? 1.0 / p.dy : 0.0;
+    double smax = 0.0;
+    bool bad = false;
+
+    if constexpr (!TWOD) {
+        const Cons<T> U0 = load_cons(p.U, plane, (size_t)gc);
+        const Cons<T> F = flux_1d(U0, kx);  // face c + 1/2
+        if constexpr (FLUXES) {
+            // lanes 1..61 hold faces x0 - 1/2 .. x0 + 59 + 1/2
+            if (lane >= 1 && lane <= 1 + kStrip && c >= -1 && c <= p.nx - 1)
+                store_face(p.Fx, (size_t)(p.nx + 1), (size_t)(c + 1), F);
+            return;
+        }
+        const Cons<T> Fm = lane_shift(F, -1);
+        Cons<T> Un = update(U0, cx, F, Fm);
+        kick(Un, p, dt, c, 0, false);
+        if (own) {
+            store_cons(p.Unew, plane, (size_t)c, Un);
+            const Prim<T> wn = to_prim(Un);
+            smax = signal_rate<T, false>(wn, idx, idy);
+            bad = !physical(wn);
+        }
+    } else {
+        const T ky = T(dt / (2.0 * p.dy)), cy = T(dt / p.dy);
+        const int y0 = sy * p.ty, y1 = min(y0 + p.ty, p.ny);
+        auto load_row = [&](int r) -> Cons<T> {
+            const int gr = map_index(r, p.ny, p.bcy);
+            return load_cons(p.U, plane, (size_t)gr * p.nx + gc);
+        };
+        Cons<T> U0 = load_row(y0 - 1), Up = load_row(y0);
+        Prim<T> Wm = to_prim(load_row(y0 - 2)), W0 = to_prim(U0), Wp = to_prim(Up);
+        Face<T> yhi_prev;   // high y-face state of the cell below, in swapped (normal = x) form
+        Cons<T> F_prev;     // F(c + 1/2, r - 1)
+        Cons<T> G_prev;     // G(c, r - 3/2)
+        Cons<T> Uc_prev;    // U^n(c, r - 1)
+
+        for (int r = y0 - 1; r <= y1; ++r) {
+            const Cons<T> Unext = (r + 2 <= y1 + 1) ? load_row(r + 2) : Up;
+
+            // face states of (c, r): x neighbours from the adjacent lanes, y from the row window
+            const Faces<T> fs = face_states<T, true>(W0, lane_shift(W0, -1), lane_shift(W0, +1), Wm, Wp, kx, ky);
+            const Face<T> xhi = make_face_x(fs.xhi);
+            const Face<T> xlo = make_face_x(fs.xlo);
+            const Face<T> yhi = make_face_x(swap(fs.yhi));
+            const Face<T> ylo = make_face_x(swap(fs.ylo));
+
+            const Cons<T> F = hll_x(xhi, lane_shift(xlo, +1));  // x face c + 1/2, row r
+            Cons<T> G{};                                        // y face r - 1/2
+            if (r >= y0) G = swap(hll_x(yhi_prev, ylo));
+
+            if constexpr (FLUXES) {
+                if (r >= y0 && r < y1 && lane >= 1 && lane <= 1 + kStrip && c >= -1 && c <= p.nx - 1)
+                    store_face(p.Fx, (size_t)(p.nx + 1) * p.ny, (size_t)r * (p.nx + 1) + (c + 1), F);
+                if (r >= y0 && own)
+                    store_face(p.Fy, (size_t)p.nx * (p.ny + 1), (size_t)r * p.nx + c, G);
+            } else {
+                if (r >= y0 + 1) {  // update cell (c, r - 1)
+                    const Cons<T> Fm = lane_shift(F_prev, -1);
+                    Cons<T> Un = update(update(Uc_prev, cx, F_prev, Fm), cy, G, G_prev);
+                    kick(Un, p, dt, c, r - 1, true);
+                    if (own) {
+                        store_cons(p.Unew, plane, (size_t)(r - 1) * p.nx + c, Un);
+                        const Prim<T> wn = to_prim(Un);
+                        smax = fmax(smax, signal_rate<T, true>(wn, idx, idy));
+                        bad = bad || !physical(wn);
+                    }
+                }
+            }
+            F_prev = F;
+            G_prev = G;
+            yhi_prev = yhi;
+            Uc_prev = U0;
+            Wm = W0;
+            W0 = Wp;
+            U0 = Up;
+            Up = Unext;
+            Wp = to_prim(Unext);
+        }
+        if constexpr (FLUXES) return;
+    }
+
+    smax = wave_max(smax);
+    if (lane == 0) atomic_max_pos(&p.slots[p.s_out].s_bits, smax);
+    if (__any(bad) && lane == 0) atomicOr(p.flag, 1);
+}
+
+template <typename T>
+hipError_t launch_step(const StepArgs<T>& a, bool twod, bool fluxes, hipStream_t s)
+{
+    const int nwaves = a.nstrips * a.nsegs;
+    const dim3 grid((nwaves + kWaves - 1) / kWaves), block(64 * kWaves);
+    if (twod) {
+        if (fluxes) sweep_kernel<T, true, true><<<grid, block, 0, s>>>(a);
+        else sweep_kernel<T, true, false><<<grid, block, 0, s>>>(a);
+    } else {
+        if (fluxes) sweep_kernel<T, false, true><<<grid, block, 0, s>>>(a);
+        else sweep_kernel<T, false, false><<<grid, block, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+// ---- primitive -> conserved, with validation ------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void init_kernel(const T* __restrict__ W, T* __restrict__ U, int64_t n,
+                                                   int* flag)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (c < n) {
+        const Prim<T> w = {W[c], W[n + c], W[2 * n + c], W[3 * n + c], W[4 * n + c], W[5 * n + c]};
+        bad = !physical(w);
+        store_cons(U, (size_t)n, (size_t)c, to_cons(w));
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+template <typename T>
+hipError_t launch_init(const T* W, T* U, int64_t n, int* flag, hipStream_t s)
+{
+    const int64_t blocks = (n + 255) / 256;
+    init_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(W, U, n, flag);
+    return hipGetLastError();
+}
+
+// ---- standalone CFL-rate reduction ----------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void maxspeed_kernel(const T* __restrict__ U, int64_t n, int twod,
+                                                       double idx, double idy, Slot* slot, int* flag)
+{
+    double s = 0.0;
+    bool bad = false;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const Prim<T> w = to_prim(load_cons(U, (size_t)n, (size_t)c));
+        s = fmax(s, twod ? signal_rate<T, true>(w, idx, idy) : signal_rate<T, false>(w, idx, idy));
+        bad = bad || !physical(w);
+    }
+    s = wave_max(s);
+    if ((threadIdx.x & 63) == 0) atomic_max_pos(&slot->s_bits, s);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+template <typename T>
+hipError_t launch_maxspeed(const T* U, int nx, int ny, double dx, double dy, Slot* slot, int* flag,
+                           hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    maxspeed_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(U, n, ny > 1, 1.0 / dx,
+                                                                    ny > 1 ? 1.0 / dy : 0.0, slot, flag);
+    return hipGetLastError();
+}
+
+__global__ void reset_kernel(Slot* slots, int nslots, double t0)
+{
+    const int i = threadIdx.x;
+    if (i < nslots) {
+        slots[i].s_bits = 0ull;
+        slots[i].t = t0;
+    }
+}
+
+hipError_t launch_reset(Slot* slots, int nslots, double t0, hipStream_t s)
+{
+    reset_kernel<<<1, 64, 0, s>>>(slots, nslots, t0);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void copy_kernel(const T* __restrict__ a, T* __restrict__ b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+template <typename T>
+hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    copy_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+#define CSH_INSTANTIATE(T)                                                                         \
+    template hipError_t launch_step<T>(const StepArgs<T>&, bool, bool, hipStream_t);               \
+    template hipError_t launch_init<T>(const T*, T*, int64_t, int*, hipStream_t);                  \
+    template hipError_t launch_maxspeed<T>(const T*, int, int, double, double, Slot*, int*,        \
+                                           hipStream_t);                                           \
+    template hipError_t launch_copy<T>(const T*, T*, int64_t, hipStream_t);
+
+CSH_INSTANTIATE(double)
+CSH_INSTANTIATE(float)
+
+}  // namespace csh

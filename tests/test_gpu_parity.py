@@ -1,0 +1,224 @@
+"""Parity of the HIP sweep with the CPU oracle on seeded inputs.
+
+Tolerances (FP64): max relative error (per-field metric of tests/parity.py)
+<= 1e-12 after one step and <= 1e-10 after 100 steps.  Grid sizes span several
+60-column strips and row segments with ragged tails; the full-size disc is
+checked on sampled cells the oracle computes one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import exact_riemann as er
+import workloads as wl
+import paper_1210_5246_amd as csh
+from parity import max_rel_error
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL1 = 1e-12
+TOL100 = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ogrid(w):
+    return oracle.Grid(w.nx, w.ny, w.dx, w.dy, w.bcx, w.bcy, w.x0, w.y0, w.vc, w.rc)
+
+
+def gpu_grid(w, dtype=torch.float64):
+    W = torch.from_numpy(np.ascontiguousarray(w.W)).to(DEV, dtype)
+    g = csh.Grid(W, w.dx, w.dy, (w.bcx, w.bcy))
+    if w.vc:
+        g.set_potential(w.vc, w.rc, w.x0, w.y0)
+    return g
+
+
+def rect_periodic(nx, ny, seed, bc=(0, 0)):
+    n = max(nx, ny, 64)   # the smooth generator needs a few widths of room
+    w = wl.periodic(n, seed)
+    w.W = np.ascontiguousarray(w.W[:, :ny, :nx])
+    w.nx, w.ny = nx, ny
+    w.dx, w.dy = 1.0 / nx, 1.3 / ny
+    w.bcx, w.bcy = bc
+    return w
+
+
+def test_init_state_matches_oracle():
+    w = rect_periodic(250, 77, 21)
+    say("init_state 250x77")
+    g = gpu_grid(w)
+    U = oracle.cons_field(w.W)
+    # fused multiply-add on the GPU vs unfused in the oracle: a few ulp,
+    # measured per field (Exy = Pxy + rho u v cancels towards zero)
+    assert max_rel_error(g.U.cpu().numpy(), U) <= 1e-15
+
+
+def test_nonphysical_input_is_rejected():
+    w = rect_periodic(70, 20, 22)
+    w.W[3, 5, 7] = -1.0
+    say("nonphysical init")
+    with pytest.raises(csh.NonPhysicalState):
+        gpu_grid(w)
+
+
+@pytest.mark.parametrize("shape", [(250, 77), (61, 5), (7, 130), (1, 3)])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
+def test_one_step_2d(shape, bc):
+    nx, ny = shape
+    w = rect_periodic(nx, ny, 23, bc)
+    say("one step 2d", shape, bc)
+    g = gpu_grid(w)
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    s_o = oracle.max_signal_speed(og, U0)
+    s_g = g.max_signal_speed()
+    assert s_g == pytest.approx(s_o, rel=1e-14)
+    dt = 0.8 / s_o
+    ref = oracle.step(og, dt, U0)
+    out = g.step(dt).cpu().numpy()
+    assert max_rel_error(out, ref) <= TOL1
+    # fused CFL rate of the output
+    assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 5, 59, 60, 61, 256, 1000])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_one_step_1d(n, bc):
+    w = wl.sod(max(n, 2))
+    w.W = np.ascontiguousarray(wl.periodic(64, 24).W[:, 3, :].repeat(16, axis=1)[:, :n])
+    w.nx, w.dx, w.bcx, w.bcy = n, 1.0 / n, bc, bc
+    say("one step 1d", n, bc)
+    g = gpu_grid(w)
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    dt = 0.8 / oracle.max_signal_speed(og, U0)
+    assert max_rel_error(g.step(dt).cpu().numpy(), oracle.step(og, dt, U0)) <= TOL1
+
+
+def test_fluxes_match_oracle():
+    w = rect_periodic(130, 70, 25, (1, 0))
+    say("fluxes 130x70")
+    g = gpu_grid(w)
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    dt = 0.8 / oracle.max_signal_speed(og, U0)
+    Fx_o, Fy_o = oracle.fluxes(og, dt, U0)
+    Fx, Fy = g.fluxes(dt)
+    for got, ref in ((Fx, Fx_o), (Fy, Fy_o)):
+        got = got.cpu().numpy()
+        scale = np.abs(ref).reshape(6, -1).max(axis=1)[:, None, None]
+        assert (np.abs(got - ref) / scale).max() <= 1e-13
+
+
+def test_hundred_steps_periodic_1024():
+    """The 1024^2 periodic workload, 100 steps at CFL 0.8 with the timestep
+    chosen on the device, against the oracle's own CFL loop."""
+    w = wl.periodic(1024, 2, 100)
+    say("periodic 1024^2 x 100 (oracle on CPU first)")
+    og = ogrid(w)
+    ref, dts_o = oracle.run_cfl(og, oracle.cons_field(w.W), nsteps=100, cfl=0.8)
+    g = gpu_grid(w)
+    dts = g.run_cfl(100, 0.8).cpu().numpy()
+    np.testing.assert_allclose(dts, dts_o, rtol=1e-12)
+    assert max_rel_error(g.U.cpu().numpy(), ref) <= TOL100
+
+
+def test_host_dt_steps_equal_device_cfl_run():
+    w = wl.periodic(192, 26, 12)
+    say("host-dt loop vs device run_cfl")
+    g1 = gpu_grid(w)
+    U = g1.U.clone()
+    dts = []
+    for _ in range(12):
+        dt = 0.8 / g1.max_signal_speed(U)
+        U = g1.step(dt, U)
+        dts.append(dt)
+    g2 = gpu_grid(w)
+    dts2 = g2.run_cfl(12, 0.8).cpu().numpy()
+    np.testing.assert_allclose(dts2, dts, rtol=1e-15)
+    assert torch.equal(U, g2.U)
+    # replaying the captured graph from the same start gives the same answer
+    g3 = gpu_grid(w)
+    start = g3.U.clone()
+    g3.run_cfl(12, 0.8)
+    first = g3.U.clone()
+    g3.U.copy_(start)
+    g3.run_cfl(12, 0.8)
+    assert torch.equal(first, g3.U)
+
+
+def test_sod_tube_to_t02():
+    """Sec. 4.1 tube, 256 cells, outflow, CFL 0.8 to t = 0.2 with the last step
+    clipped on the device; against the oracle and the exact gamma = 3 solution."""
+    w = wl.sod(256)
+    say("sod 256 -> t=0.2")
+    og = ogrid(w)
+    ref, dts_o = oracle.run_cfl(og, oracle.cons_field(w.W), cfl=0.8, t_end=0.2)
+    g = gpu_grid(w)
+    dts = g.run_cfl(len(dts_o) + 7, 0.8, t_end=0.2).cpu().numpy()
+    assert np.all(dts[len(dts_o):] == 0.0)
+    np.testing.assert_allclose(dts[:len(dts_o)], dts_o, rtol=1e-12)
+    U = g.U.cpu().numpy()
+    assert max_rel_error(U, ref) <= TOL100
+    assert np.all(U[2] == 0.0) and np.all(U[4] == 0.0)
+    Wg = oracle.prim_field(U)
+    ex = er.sod_bme_solution(w.extra["x"], 0.2)
+    assert np.abs(Wg[0] - ex[0]).mean() < 6e-3
+
+
+def test_disc_with_potential_full_grid_256():
+    w = wl.disc(256, 3, 10)
+    say("disc 256^2 x 10 with potential")
+    og = ogrid(w)
+    ref, dts_o = oracle.run_cfl(og, oracle.cons_field(w.W), nsteps=10)
+    g = gpu_grid(w)
+    dts = g.run_cfl(10, 0.8).cpu().numpy()
+    np.testing.assert_allclose(dts, dts_o, rtol=1e-12)
+    assert max_rel_error(g.U.cpu().numpy(), ref) <= 1e-11
+
+
+def sample_cells(nx, ny, k, seed):
+    r = np.random.default_rng(seed)
+    cells = set(r.integers(0, nx * ny, size=k).tolist())
+    for j in (0, 1, ny // 2, ny - 2, ny - 1):           # boundaries, strip and segment seams
+        for i in (0, 1, 59, 60, 61, nx // 2, nx - 2, nx - 1):
+            cells.add(j * nx + i)
+    return np.array(sorted(cells), dtype=np.int64)
+
+
+def test_disc_4096_one_step_sampled():
+    """Full-size disc (4096^2, FP64, outflow, fixed potential): one step in the
+    launch configuration of the benchmark, checked on sampled cells."""
+    w = wl.disc(4096, 3, 1)
+    say("disc 4096^2 one step, sampled")
+    g = gpu_grid(w)
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    s = g.max_signal_speed()
+    assert s == pytest.approx(oracle.max_signal_speed(og, U0), rel=1e-14)
+    dt = 0.8 / s
+    out = g.step(dt).cpu().numpy().reshape(6, -1)
+    cells = sample_cells(4096, 4096, 3000, 31)
+    ref = oracle.step_cells(og, dt, U0, cells).T
+    assert max_rel_error(out[:, cells], ref) <= TOL1
+
+
+def test_fp32_twin_close_to_fp64():
+    """The FP32 instantiation on the disc shape: reported accuracy, loose bound."""
+    w = wl.disc(512, 3, 5)
+    say("fp32 disc 512^2 x 5")
+    og = ogrid(w)
+    ref, _ = oracle.run_cfl(og, oracle.cons_field(w.W), nsteps=5)
+    g = gpu_grid(w, torch.float32)
+    g.run_cfl(5, 0.8)
+    err = max_rel_error(g.U.double().cpu().numpy(), ref)
+    say("fp32 max rel error after 5 steps:", err)
+    assert err < 1e-3
