@@ -1,0 +1,89 @@
+"""Differentiable sweeps: a ``torch.autograd.Function`` over many steps of the
+HIP sweep, with the hand-written adjoint (``csh_adjoint_step``) in backward.
+
+Forward: primitive fields W0 -> conserved U0 (``csh_init_state``), then
+``nsteps`` steps with the CFL timestep chosen on the device (``csh_run_cfl``),
+keeping the state every ``checkpoint_every`` steps and the timesteps taken.
+Backward: the timesteps are frozen (the gradient is that of the map with the
+recorded dt list); segment by segment from the last, the states of the segment
+are recomputed from its checkpoint with those timesteps (``csh_step``) and the
+adjoint steps run in reverse; finally ``csh_init_state_adjoint`` carries the
+gradient from U0 back to W0.  All arithmetic runs in the library's kernels;
+this module only sequences the calls and holds the checkpoints.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import BC_PERIODIC, Grid
+
+
+class AdjointSweep(torch.autograd.Function):
+    """U_n = S_{dt_{n-1}} o ... o S_{dt_0} (U(W0)); differentiable in W0."""
+
+    @staticmethod
+    def forward(ctx, W0: torch.Tensor, dx: float, dy: float, bc, nsteps: int, checkpoint_every: int,
+                cfl: float = 0.8, potential=None, dts=None):
+        g = Grid(W0.detach().contiguous(), dx, dy, bc)
+        if potential is not None:
+            g.set_potential(*potential)
+        K = max(1, int(checkpoint_every))
+        U = g.U
+        log = torch.empty(K, dtype=torch.float64, device=U.device)  # one buffer: the captured graph is reused
+        ckpts, seg_dts = [], []
+        if dts is not None:  # replay a given timestep list
+            dts = [float(d) for d in dts]
+            assert len(dts) == nsteps
+        done = 0
+        while done < nsteps:
+            k = min(K, nsteps - done)
+            ckpts.append(U.clone())
+            if dts is None:
+                seg = g.run_cfl(k, cfl, U=U, dt_log=log).cpu().tolist()
+            else:
+                seg = dts[done:done + k]
+                V = U
+                for dt in seg:
+                    V = g.step(dt, V)
+                U.copy_(V)
+            seg_dts.append(seg)
+            done += k
+        ctx.grid = g
+        ctx.ckpts = ckpts
+        ctx.seg_dts = seg_dts
+        ctx.save_for_backward(W0)
+        all_dts = torch.tensor([d for seg in seg_dts for d in seg], dtype=torch.float64)
+        ctx.mark_non_differentiable(all_dts)
+        return U.clone(), all_dts
+
+    @staticmethod
+    def backward(ctx, gU: torch.Tensor, _gdts=None):
+        (W0,) = ctx.saved_tensors
+        g = ctx.grid
+        lam = gU.contiguous().to(torch.float64)
+        for ck, seg in zip(reversed(ctx.ckpts), reversed(ctx.seg_dts)):
+            states = [ck]
+            for dt in seg[:-1]:
+                states.append(g.step(dt, states[-1]))
+            for U, dt in zip(reversed(states), reversed(seg)):
+                lam = g.adjoint_step(dt, U, lam)
+        lamW = g.init_state_adjoint(W0.detach().contiguous(), lam)
+        return lamW, None, None, None, None, None, None, None, None
+
+
+def sweep(W0: torch.Tensor, dx: float, dy: float = 1.0, bc=(BC_PERIODIC, BC_PERIODIC), nsteps: int = 1,
+          checkpoint_every: int = 20, cfl: float = 0.8, potential=None, dts=None) -> torch.Tensor:
+    """Differentiable ``nsteps``-step sweep of the primitive fields ``W0``;
+    returns (final conserved state, timesteps taken as a CPU float64 tensor)."""
+    return AdjointSweep.apply(W0, dx, dy, bc, nsteps, checkpoint_every, cfl, potential, dts)
+
+
+def run_frozen(W0: torch.Tensor, dx: float, dy: float, bc, dts, potential=None) -> torch.Tensor:
+    """Forward only, with a given timestep list (for finite-difference checks)."""
+    g = Grid(W0.contiguous(), dx, dy, bc)
+    if potential is not None:
+        g.set_potential(*potential)
+    U = g.U
+    for dt in dts:
+        U = g.step(float(dt), U)
+    return U

@@ -379,4 +379,188 @@ CSH_HD C kick_vjp(const C& lb, double h, double ax, double ay)
     return o;
 }
 
+// ---- per-cell bodies of the adjoint kernels ----------------------------------------------
+
+struct AdjArgs {
+    int nx, ny, bcx, bcy;
+    int ex, ey;          // extended grid: ex = nx + 2, ey = ny + 2 (1-D: 1)
+    double dx, dy, dt;
+    double vc2, rc2, x0, y0;
+    const double* U;     // [6][ny][nx]
+    const double* lam1;  // lam^{n+1}
+    double* lam0;        // lam^n
+    double* FS;          // [4 faces][6][ext]
+    double* FSb;         // [4][6][ext]
+    double* Cs;          // [5 roles][6][ext]
+};
+
+enum { XHI = 0, XLO = 1, YHI = 2, YLO = 3 };
+enum { SELF = 0, LEFT = 1, RIGHT = 2, DOWN = 3, UP = 4 };
+
+CSH_HD P load_p(const double* B, size_t plane, size_t slot, size_t idx)
+{
+    const double* b = B + slot * 6 * plane;
+    return {b[idx], b[plane + idx], b[2 * plane + idx], b[3 * plane + idx], b[4 * plane + idx], b[5 * plane + idx]};
+}
+CSH_HD void store_p(double* B, size_t plane, size_t slot, size_t idx, const P& v)
+{
+    double* b = B + slot * 6 * plane;
+    b[idx] = v.r;
+    b[plane + idx] = v.u;
+    b[2 * plane + idx] = v.v;
+    b[3 * plane + idx] = v.pxx;
+    b[4 * plane + idx] = v.pxy;
+    b[5 * plane + idx] = v.pyy;
+}
+
+// primitive state of the (possibly ghost) cell (i, j)
+CSH_HD P prim_at(const AdjArgs& a, int i, int j, bool twod)
+{
+    const int gi = map_index(i, a.nx, a.bcx);
+    const int gj = twod ? map_index(j, a.ny, a.bcy) : 0;
+    return to_prim(load_cons<double>(a.U, (size_t)a.nx * a.ny, (size_t)gj * a.nx + gi));
+}
+
+CSH_HD size_t ext_index(const AdjArgs& a, int i, int j) { return (size_t)(j + (a.ey > 1 ? 1 : 0)) * a.ex + (i + 1); }
+
+// lam' of interior cell (i, j): the kick's transpose applied to lam^{n+1}
+CSH_HD C lam_prime(const AdjArgs& a, int i, int j, bool twod)
+{
+    const C l = load_cons<double>(a.lam1, (size_t)a.nx * a.ny, (size_t)j * a.nx + i);
+    if (a.vc2 == 0.0) return l;
+    const double x = a.x0 + (i + 0.5) * a.dx;
+    const double y = twod ? a.y0 + (j + 0.5) * a.dy : 0.0;
+    const double f = -a.vc2 / (x * x + y * y + a.rc2);
+    return kick_vjp(l, a.dt, f * x, f * y);
+}
+
+template <bool TWOD>
+CSH_HD void faces_cell(const AdjArgs& a, int i, int j)
+{
+    const double kx = a.dt / (2.0 * a.dx), ky = TWOD ? a.dt / (2.0 * a.dy) : 0.0;
+    const P W0 = prim_at(a, i, j, TWOD);
+    const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
+    const P Wm = TWOD ? prim_at(a, i, j - 1, TWOD) : W0, Wp = TWOD ? prim_at(a, i, j + 1, TWOD) : W0;
+    const Faces<double> f = face_states<double, TWOD>(W0, Wl, Wr, Wm, Wp, kx, ky);
+    const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
+    store_p(a.FS, ne, XHI, e, f.xhi);
+    store_p(a.FS, ne, XLO, e, f.xlo);
+    if (TWOD) {
+        store_p(a.FS, ne, YHI, e, f.yhi);
+        store_p(a.FS, ne, YLO, e, f.ylo);
+    }
+}
+
+CSH_HD C csub(const C& p, const C& q, double s)
+{
+    return {s * (p.r - q.r), s * (p.mx - q.mx), s * (p.my - q.my), s * (p.exx - q.exx), s * (p.exy - q.exy),
+            s * (p.eyy - q.eyy)};
+}
+
+template <bool TWOD>
+CSH_HD void hll_cell(const AdjArgs& a, int i, int j)
+{
+    const size_t ne = (size_t)a.ex * a.ey;
+    const size_t e = ext_index(a, i, j);
+    const C z = zero_c();
+    // x face i + 1/2 in an interior row: between extended cells (i, j) and (i + 1, j)
+    if (i <= a.nx - 1 && (!TWOD || (j >= 0 && j < a.ny))) {
+        const int jj = TWOD ? j : 0;
+        const C lp = (i + 1 <= a.nx - 1) ? lam_prime(a, i + 1, jj, TWOD) : z;
+        const C lm = (i >= 0) ? lam_prime(a, i, jj, TWOD) : z;
+        const C Fb = csub(lp, lm, a.dt / a.dx);
+        P wlb = zero_p(), wrb = zero_p();
+        hll_vjp(load_p(a.FS, ne, XHI, e), load_p(a.FS, ne, XLO, e + 1), Fb, wlb, wrb);
+        store_p(a.FSb, ne, XHI, e, wlb);
+        store_p(a.FSb, ne, XLO, e + 1, wrb);
+    }
+    if (TWOD && j <= a.ny - 1 && i >= 0 && i < a.nx) {
+        const C lp = (j + 1 <= a.ny - 1) ? lam_prime(a, i, j + 1, true) : z;
+        const C lm = (j >= 0) ? lam_prime(a, i, j, true) : z;
+        const C Gb = csub(lp, lm, a.dt / a.dy);
+        P wlb = zero_p(), wrb = zero_p();
+        hll_vjp(swap(load_p(a.FS, ne, YHI, e)), swap(load_p(a.FS, ne, YLO, e + a.ex)), swap(Gb), wlb, wrb);
+        store_p(a.FSb, ne, YHI, e, swapb(wlb));
+        store_p(a.FSb, ne, YLO, e + a.ex, swapb(wrb));
+    }
+}
+
+template <bool TWOD>
+CSH_HD void cells_cell(const AdjArgs& a, int i, int j)
+{
+    const double kx = a.dt / (2.0 * a.dx), ky = TWOD ? a.dt / (2.0 * a.dy) : 0.0;
+    const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
+    const P W0 = prim_at(a, i, j, TWOD);
+    const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
+    const P Wm = TWOD ? prim_at(a, i, j - 1, TWOD) : W0, Wp = TWOD ? prim_at(a, i, j + 1, TWOD) : W0;
+    Faces<double> fb;
+    fb.xhi = load_p(a.FSb, ne, XHI, e);
+    fb.xlo = load_p(a.FSb, ne, XLO, e);
+    if (TWOD) {
+        fb.yhi = load_p(a.FSb, ne, YHI, e);
+        fb.ylo = load_p(a.FSb, ne, YLO, e);
+    } else {
+        fb.yhi = fb.ylo = zero_p();
+    }
+    P b0 = zero_p(), bl = zero_p(), br = zero_p(), bm = zero_p(), bp = zero_p();
+    face_states_vjp<TWOD>(W0, Wl, Wr, Wm, Wp, kx, ky, fb, b0, bl, br, bm, bp);
+    store_p(a.Cs, ne, SELF, e, b0);
+    store_p(a.Cs, ne, LEFT, e, bl);
+    store_p(a.Cs, ne, RIGHT, e, br);
+    if (TWOD) {
+        store_p(a.Cs, ne, DOWN, e, bm);
+        store_p(a.Cs, ne, UP, e, bp);
+    }
+}
+
+// positions p in [-2, n+1] (the ghost-padded range the stencil reads) with
+// map(p) == i; returns their count (at most 5)
+CSH_HD int preimages(int i, int n, int bc, int* p)
+{
+    int k = 0;
+    if (bc == 0) {  // periodic: p = i + m n
+        for (int m = -3; m <= 3; ++m) {
+            const int q = i + m * n;
+            if (q >= -2 && q <= n + 1) p[k++] = q;
+        }
+    } else {        // outflow: clamp(p) == i
+        const int lo = (i == 0) ? -2 : i, hi = (i == n - 1) ? n + 1 : i;
+        for (int q = lo; q <= hi; ++q) p[k++] = q;
+    }
+    return k;
+}
+
+// sum of the slots that land on padded position (pi, pj)
+template <bool TWOD>
+CSH_HD P pad_sum(const AdjArgs& a, int pi, int pj)
+{
+    const size_t ne = (size_t)a.ex * a.ey;
+    auto in_ext = [&](int i, int j) { return i >= -1 && i <= a.nx && (!TWOD || (j >= -1 && j <= a.ny)); };
+    P s = zero_p();
+    if (in_ext(pi, pj)) acc(s, load_p(a.Cs, ne, SELF, ext_index(a, pi, pj)));
+    if (in_ext(pi + 1, pj)) acc(s, load_p(a.Cs, ne, LEFT, ext_index(a, pi + 1, pj)));
+    if (in_ext(pi - 1, pj)) acc(s, load_p(a.Cs, ne, RIGHT, ext_index(a, pi - 1, pj)));
+    if (TWOD) {
+        if (in_ext(pi, pj + 1)) acc(s, load_p(a.Cs, ne, DOWN, ext_index(a, pi, pj + 1)));
+        if (in_ext(pi, pj - 1)) acc(s, load_p(a.Cs, ne, UP, ext_index(a, pi, pj - 1)));
+    }
+    return s;
+}
+
+template <bool TWOD>
+CSH_HD void gather_cell(const AdjArgs& a, int i, int j)
+{
+    int px[5], py[5];
+    const int nx_ = preimages(i, a.nx, a.bcx, px);
+    const int ny_ = TWOD ? preimages(j, a.ny, a.bcy, py) : 1;
+    if (!TWOD) py[0] = 0;
+    P wb = zero_p();
+    for (int u = 0; u < nx_; ++u)
+        for (int v = 0; v < ny_; ++v) acc(wb, pad_sum<TWOD>(a, px[u], py[v]));
+    const size_t plane = (size_t)a.nx * a.ny, c = (size_t)j * a.nx + i;
+    C out = lam_prime(a, i, j, TWOD);
+    to_prim_vjp(load_cons<double>(a.U, plane, c), wb, out);
+    store_cons(a.lam0, plane, c, out);
+}
+
 }  // namespace csh

@@ -1,0 +1,121 @@
+// CPU harness for the adjoint: runs the per-cell bodies of the adjoint kernels
+// and the forward face/flux arithmetic in host loops, so the tests can check
+// the hand-written reverse pass against finite differences and the oracle's
+// dense Jacobian without a GPU.  Test infrastructure only.
+#include <cstring>
+#include <vector>
+
+#include "csh_adjoint.h"
+
+using namespace csh;
+
+static AdjArgs make_args(int nx, int ny, int bcx, int bcy, double dx, double dy, double dt, double vc, double rc,
+                         double x0, double y0, const double* U)
+{
+    AdjArgs a{};
+    a.nx = nx;
+    a.ny = ny;
+    a.bcx = bcx;
+    a.bcy = bcy;
+    a.ex = nx + 2;
+    a.ey = ny > 1 ? ny + 2 : 1;
+    a.dx = dx;
+    a.dy = ny > 1 ? dy : 1.0;
+    a.dt = dt;
+    a.vc2 = vc * vc;
+    a.rc2 = rc * rc;
+    a.x0 = x0;
+    a.y0 = y0;
+    a.U = U;
+    return a;
+}
+
+template <bool TWOD>
+static void adjoint_loops(AdjArgs& a)
+{
+    const int j0 = TWOD ? -1 : 0, j1 = TWOD ? a.ny : 0;
+    for (int j = j0; j <= j1; ++j)
+        for (int i = -1; i <= a.nx; ++i) faces_cell<TWOD>(a, i, j);
+    for (int j = j0; j <= j1; ++j)
+        for (int i = -1; i <= a.nx; ++i) hll_cell<TWOD>(a, i, j);
+    for (int j = j0; j <= j1; ++j)
+        for (int i = -1; i <= a.nx; ++i) cells_cell<TWOD>(a, i, j);
+    for (int j = 0; j < (TWOD ? a.ny : 1); ++j)
+        for (int i = 0; i < a.nx; ++i) gather_cell<TWOD>(a, i, j);
+}
+
+extern "C" int host_adjoint_step(int nx, int ny, int bcx, int bcy, double dx, double dy, double dt, double vc,
+                                 double rc, double x0, double y0, const double* U, const double* lam1, double* lam0)
+{
+    AdjArgs a = make_args(nx, ny, bcx, bcy, dx, dy, dt, vc, rc, x0, y0, U);
+    const size_t ne = (size_t)a.ex * a.ey;
+    std::vector<double> ws(78 * ne, 0.0);
+    a.FS = ws.data();
+    a.FSb = ws.data() + 24 * ne;
+    a.Cs = ws.data() + 48 * ne;
+    a.lam1 = lam1;
+    a.lam0 = lam0;
+    if (ny > 1) adjoint_loops<true>(a);
+    else adjoint_loops<false>(a);
+    return 0;
+}
+
+// the forward step with the same face-state, HLL, update and kick arithmetic
+template <bool TWOD>
+static void step_loops(AdjArgs& a, double* Un)
+{
+    const int j0 = TWOD ? -1 : 0, j1 = TWOD ? a.ny : 0;
+    for (int j = j0; j <= j1; ++j)
+        for (int i = -1; i <= a.nx; ++i) faces_cell<TWOD>(a, i, j);
+    const size_t ne = (size_t)a.ex * a.ey, plane = (size_t)a.nx * a.ny;
+    const double cx = a.dt / a.dx, cy = a.dt / a.dy;
+    for (int j = 0; j < (TWOD ? a.ny : 1); ++j)
+        for (int i = 0; i < a.nx; ++i) {
+            const size_t e = ext_index(a, i, j);
+            const C Fp = hll_x(make_face_x(load_p(a.FS, ne, XHI, e)), make_face_x(load_p(a.FS, ne, XLO, e + 1)));
+            const C Fm = hll_x(make_face_x(load_p(a.FS, ne, XHI, e - 1)), make_face_x(load_p(a.FS, ne, XLO, e)));
+            C u = update(load_cons<double>(a.U, plane, (size_t)j * a.nx + i), cx, Fp, Fm);
+            if (TWOD) {
+                const C Gp = swap(hll_x(make_face_x(swap(load_p(a.FS, ne, YHI, e))),
+                                        make_face_x(swap(load_p(a.FS, ne, YLO, e + a.ex)))));
+                const C Gm = swap(hll_x(make_face_x(swap(load_p(a.FS, ne, YHI, e - a.ex))),
+                                        make_face_x(swap(load_p(a.FS, ne, YLO, e)))));
+                u = update(u, cy, Gp, Gm);
+            }
+            if (a.vc2 != 0.0) {
+                const double x = a.x0 + (i + 0.5) * a.dx, y = TWOD ? a.y0 + (j + 0.5) * a.dy : 0.0;
+                const double f = -a.vc2 / (x * x + y * y + a.rc2), ax = f * x, ay = f * y, h = a.dt;
+                const double mx = u.mx, my = u.my;
+                u.mx = mx + h * u.r * ax;
+                u.my = my + h * u.r * ay;
+                u.exx = u.exx + h * ax * (2.0 * mx + h * u.r * ax);
+                u.exy = u.exy + h * (ax * my + mx * ay + h * u.r * ax * ay);
+                u.eyy = u.eyy + h * ay * (2.0 * my + h * u.r * ay);
+            }
+            store_cons(Un, plane, (size_t)j * a.nx + i, u);
+        }
+}
+
+extern "C" int host_step(int nx, int ny, int bcx, int bcy, double dx, double dy, double dt, double vc, double rc,
+                         double x0, double y0, const double* U, double* Un)
+{
+    AdjArgs a = make_args(nx, ny, bcx, bcy, dx, dy, dt, vc, rc, x0, y0, U);
+    const size_t ne = (size_t)a.ex * a.ey;
+    std::vector<double> fs(24 * ne, 0.0);
+    a.FS = fs.data();
+    if (ny > 1) step_loops<true>(a, Un);
+    else step_loops<false>(a, Un);
+    return 0;
+}
+
+// W -> U and its transpose, per cell
+extern "C" void host_init_adjoint(int64_t n, const double* W, const double* lamU, double* lamW)
+{
+    for (int64_t c = 0; c < n; ++c) {
+        const P w = {W[c], W[n + c], W[2 * n + c], W[3 * n + c], W[4 * n + c], W[5 * n + c]};
+        P wb = zero_p();
+        to_cons_vjp(w, load_cons<double>(lamU, (size_t)n, (size_t)c), wb);
+        const double v[6] = {wb.r, wb.u, wb.v, wb.pxx, wb.pxy, wb.pyy};
+        for (int m = 0; m < 6; ++m) lamW[m * n + c] = v[m];
+    }
+}

@@ -89,7 +89,7 @@ def test_one_step_2d(shape, bc):
     assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
 
 
-@pytest.mark.parametrize("n", [1, 5, 59, 60, 61, 256, 1000])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 59, 60, 61, 256, 1000])
 @pytest.mark.parametrize("bc", [0, 1])
 def test_one_step_1d(n, bc):
     w = wl.sod(max(n, 2))
