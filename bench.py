@@ -11,6 +11,7 @@ resident in HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +23,30 @@ sys.path.insert(0, ROOT)
 BYTES_PER_CELL_F64 = 96     # 6 conserved planes read + 6 written, 8 B each
 BYTES_PER_CELL_F32 = 48
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+
+
+PROFILES = os.path.join(ROOT, "profiles")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_1210_5246_amd", "csrc", f)
+                 for f in ("csh_fwd.hip", "csh_device.h", "csh_internal.h")]
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(PROFILES, f"sweep_disc{n}_f64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_source_hash") != sweep_source_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def log(*a):
@@ -78,6 +103,131 @@ def cpu_baseline(w, max_seconds=20.0):
                       f"{el:.1f} s, FP64 C oracle with {threads} OpenMP threads"}
 
 
+def bench_batched(steps=200):
+    """512 uneven tubes x 200 steps: one persistent graph launch vs the plain
+    path (per tube its own grid; per step a host round trip for the timestep
+    and one launch)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    import paper_1210_5246_amd as csh
+    t = wl.tubes(nsteps=steps)
+    W = torch.from_numpy(t.W).to("cuda")
+    b = csh.Batch(W, t.offsets)
+    U0 = b.U.clone()
+    best = b.autotune(probe_steps=8)
+    b.run(steps, 0.8)                       # records the graph
+    b.U.copy_(U0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.run(steps, 0.8)
+    e1.record()
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    Ub = b.U.cpu().numpy()
+    log(f"batched: {t_batch * 1e3:.2f} ms (workgroup {best})")
+    # plain path
+    worst = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for k in range(t.lengths.size):
+        n = int(t.lengths[k])
+        g = csh.Grid(W[:, int(t.offsets[k]):int(t.offsets[k + 1])].contiguous(), 1.0 / n, 1.0,
+                     (csh.BC_OUTFLOW, csh.BC_OUTFLOW))
+        Ug = g.U
+        for _ in range(steps):
+            Ug = g.step(0.8 / g.max_signal_speed(Ug), Ug)
+        outs.append(Ug)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for k, Ug in enumerate(outs):
+        ref = Ug.cpu().numpy()
+        got = Ub[:, int(t.offsets[k]):int(t.offsets[k + 1])]
+        worst = max(worst, float(np.abs(got - ref).max() / np.abs(ref).max()))
+    cells = int(t.offsets[-1]) * steps
+    log(f"plain: {t_plain:.2f} s; max scaled difference {worst:.1e}")
+    return {"workload": f"{t.lengths.size} tubes, lengths U{{128..4096}} (total {int(t.offsets[-1])} cells), "
+                        f"{steps} steps, own CFL dt per tube, FP64",
+            "batched_value": cells / t_batch, "plain_value": cells / t_plain, "unit": "cell-updates/s",
+            "speedup": t_plain / t_batch, "batched_ms": t_batch * 1e3, "plain_s": t_plain,
+            "workgroup": best, "max_scaled_difference": worst}
+
+
+def bench_adjoint(n=512, steps=200, K=20, ndirs=64):
+    """Gradient of 1/2 sum(rho_200 - rho*)^2 w.r.t. the initial fields: one
+    checkpointed adjoint pass vs central differences on ndirs directions
+    (2 ndirs forward runs at frozen timesteps)."""
+    import torch
+    import workloads as wl
+    import paper_1210_5246_amd as csh
+    from paper_1210_5246_amd import autograd as cag
+    w0, wt = wl.adjoint(n, 5, 6, steps, K)
+    Gt = csh.Grid(torch.from_numpy(wt.W).to("cuda"), wt.dx, wt.dy)
+    Gt.run_cfl(steps, 0.8)
+    rho_t = Gt.U[0].clone()
+    Wd = torch.from_numpy(w0.W).to("cuda")
+
+    def grad_once():
+        W0 = Wd.clone().requires_grad_(True)
+        U, dts = cag.sweep(W0, w0.dx, w0.dy, nsteps=steps, checkpoint_every=K)
+        L = 0.5 * ((U[0] - rho_t) ** 2).sum()
+        (gr,) = torch.autograd.grad(L, W0)
+        return gr, dts
+
+    grad_once()  # warm (graph capture, workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr, dts = grad_once()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    g = csh.Grid(Wd, w0.dx, w0.dy)
+    U0 = g.U.clone()
+    g.run_cfl(steps, 0.8)
+    g.U.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run_cfl(steps, 0.8)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    dirs = [torch.from_numpy(d).to("cuda") for d in wl.fd_directions(n, ndirs)]
+    eps = 1e-6
+    runner = cag.FrozenRunner(Wd, w0.dx, w0.dy, (0, 0), dts)
+    runner.run(Wd)  # records the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fds = []
+    for dd in dirs:
+        rp = runner.run(Wd + eps * dd)[0].clone()
+        rm = runner.run(Wd - eps * dd)[0]
+        fds.append(float(((rp - rm) * (0.5 * (rp + rm) - rho_t)).sum()) / (2 * eps))
+    torch.cuda.synchronize()
+    t_fd = time.perf_counter() - t0
+    worst = 0.0
+    for dd, fd in zip(dirs, fds):
+        gd = gr * dd
+        worst = max(worst, abs(fd - float(gd.sum())) / float(gd.abs().sum()))
+    log(f"adjoint: grad {t_grad:.3f} s, forward {t_fwd:.3f} s, FD({ndirs} dirs) {t_fd:.2f} s")
+    return {"workload": f"periodic {n}x{n} FP64, {steps} steps, checkpoints every {K}, "
+                        f"gradient vs central differences on {ndirs} directions (eps {eps})",
+            "adjoint_gradient_s": t_grad, "forward_s": t_fwd, "fd_gradient_s": t_fd,
+            "speedup": t_fd / t_grad, "adjoint_over_forward": t_grad / t_fwd,
+            "max_fd_deviation_over_sum_abs_terms_eps1e-6": worst}
+
+
+def copy_probe(nbytes=1 << 30):
+    """A plain device copy of known size (for calibrating the HBM byte counters)."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: {nbytes} bytes read + {nbytes} written per launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +236,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -98,6 +251,8 @@ def main():
     import paper_1210_5246_amd as csh
 
     n, K, Wm = args.n, args.steps, args.warmup
+    if args.copy_probe:
+        copy_probe()
     log(f"generating disc {n}^2")
     w = wl.disc(n, 3, K)
     cells = w.nx * w.ny
@@ -146,10 +301,11 @@ def main():
         "data": "synthetic (seeded disc-shaped input: exponential surface density, flat rotation curve, "
                 "Toomre Q=1.5, anisotropic stress, m=2 perturbation)",
         "config": {"workload": f"disc {n}x{n}, FP64, {K} CFL steps at C=0.8, outflow, fixed potential",
-                   "cells": cells, "rows_per_wave": None},
+                   "cells": cells},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n),
                      "kernel": "sweep_kernel<double, 2-D>", "kernel_ms": f64["kernel_s"] * 1e3,
+                     "kernel_source_hash": sweep_source_hash(),
                      "algorithmic_bytes_per_launch": f64["bpc"] * cells},
     }
     if "f32" in res:
@@ -157,6 +313,12 @@ def main():
         out["fp32"] = {"value": K * cells / f32["secs"], "ms_per_step": f32["secs"] / K * 1e3,
                        "kernel_ms": f32["kernel_s"] * 1e3,
                        "achieved_GBs": f32["bpc"] * cells / f32["kernel_s"] / 1e9}
+    if not args.no_batch:
+        log("batched tubes")
+        out["batched"] = bench_batched()
+    if not args.no_adjoint:
+        log("adjoint gradient")
+        out["adjoint"] = bench_adjoint()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -51,7 +51,8 @@ const char *csh_last_error(void);
 
 /*
  * Create a grid handle and convert primitive to conserved state.
- * nx >= 1, ny >= 1 (ny == 1: one-dimensional scheme, no y terms); dx, dy > 0
+ * nx >= 1, ny >= 1 (ny == 1: one-dimensional scheme, no y terms), one plane
+ * (nx ny elements) smaller than 4 GiB; dx, dy > 0
  * (dy unused in 1-D); bc_x, bc_y: CSH_BC_*; dtype: CSH_F64 or CSH_F32.
  * W: device, primitive fields [6][ny][nx], read only.  U: device, receives the
  * conserved state [6][ny][nx] (the definitions of Sec. 2).  stream: a
@@ -63,6 +64,14 @@ const char *csh_last_error(void);
  */
 int csh_init_state(csh_grid **h, int nx, int ny, double dx, double dy, int bc_x, int bc_y,
                    int dtype, const void *W, void *U, void *stream);
+
+/*
+ * Convert primitive fields W into conserved state U on an existing handle
+ * (the conversion and validation of csh_init_state; clears the handle's
+ * non-physical flag first).  W, U: device [6][ny][nx] of the handle's dtype.
+ * Synchronises.
+ */
+int csh_set_state(csh_grid *h, const void *W, void *U);
 
 /*
  * Fixed external potential of a flat rotation curve, Phi = vc^2/2 ln(R^2 + rc^2)
@@ -119,6 +128,15 @@ int csh_fluxes(csh_grid *h, double dt, const void *U, void *Fx, void *Fy);
  */
 int csh_run_cfl(csh_grid *h, int nsteps, double cfl, double t_end, void *U, void *U_work,
                 double *dt_log);
+
+/*
+ * Advance nsteps steps with given timesteps: step k uses dts[k] (device array
+ * of nsteps doubles, read when the step runs).  U is updated in place (U_work
+ * as for csh_run_cfl); captured once as a HIP graph per (nsteps, buffers, dts)
+ * and replayed.  Replays a recorded run exactly (the timesteps of csh_run_cfl's
+ * dt_log reproduce its states bit for bit).
+ */
+int csh_run_dts(csh_grid *h, int nsteps, const double *dts, void *U, void *U_work);
 
 /*
  * Adjoint of one sweep at frozen timestep dt:

@@ -46,12 +46,14 @@ _SIGNATURES = [
     ("csh_last_error", ctypes.c_char_p, []),
     ("csh_init_state", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    ("csh_set_state", ctypes.c_int, [_vp, _vp, _vp]),
     ("csh_set_potential", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("csh_step", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp]),
     ("csh_max_signal_speed", ctypes.c_int, [_vp, _vp, _dp]),
     ("csh_last_signal_speed", ctypes.c_int, [_vp, _dp]),
     ("csh_fluxes", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _vp]),
     ("csh_run_cfl", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]),
+    ("csh_run_dts", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     ("csh_adjoint_step", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _vp]),
     ("csh_init_state_adjoint", ctypes.c_int, [_vp, _vp, _vp, _vp]),
     ("csh_destroy", ctypes.c_int, [_vp]),
@@ -133,6 +135,12 @@ class Grid:
             self._h = None
 
     # -- the C entry points -----------------------------------------------------------
+    def set_state(self, W: torch.Tensor, U: torch.Tensor | None = None) -> torch.Tensor:
+        """Primitive fields -> conserved state (default into ``self.U``) on this handle."""
+        U = self.U if U is None else U
+        _check(lib().csh_set_state(self._h, _dev(W, self.dtype), _dev(U, self.dtype)))
+        return U
+
     def set_potential(self, vc: float, rc: float, x0: float, y0: float = 0.0):
         _check(lib().csh_set_potential(self._h, vc, rc, x0, y0))
 
@@ -179,6 +187,17 @@ class Grid:
         _check(lib().csh_run_cfl(self._h, int(nsteps), float(cfl), float(t_end), _dev(U, self.dtype),
                                  _dev(work, self.dtype), _dev(dt_log, torch.float64)))
         return dt_log[:nsteps]
+
+    def run_dts(self, dts: torch.Tensor, U: torch.Tensor | None = None, work: torch.Tensor | None = None):
+        """Advance ``U`` (default ``self.U``) in place with the timesteps ``dts`` (GPU float64)."""
+        U = self.U if U is None else U
+        if work is None:
+            work = getattr(self, "_work", None)
+            if work is None or work.shape != U.shape or work.dtype != U.dtype:
+                work = self._work = torch.empty_like(U)
+        _check(lib().csh_run_dts(self._h, int(dts.numel()), _dev(dts, torch.float64), _dev(U, self.dtype),
+                                 _dev(work, self.dtype)))
+        return U
 
     def adjoint_step(self, dt: float, U: torch.Tensor, lam_next: torch.Tensor,
                      out: torch.Tensor | None = None) -> torch.Tensor:

@@ -79,11 +79,27 @@ def sweep(W0: torch.Tensor, dx: float, dy: float = 1.0, bc=(BC_PERIODIC, BC_PERI
 
 
 def run_frozen(W0: torch.Tensor, dx: float, dy: float, bc, dts, potential=None) -> torch.Tensor:
-    """Forward only, with a given timestep list (for finite-difference checks)."""
+    """Forward only, with a given timestep list (for finite-difference checks):
+    one graph launch of len(dts) steps reading the timesteps on the device."""
     g = Grid(W0.contiguous(), dx, dy, bc)
     if potential is not None:
         g.set_potential(*potential)
-    U = g.U
-    for dt in dts:
-        U = g.step(float(dt), U)
-    return U
+    d = torch.as_tensor(dts, dtype=torch.float64).to(g.U.device).contiguous()
+    return g.run_dts(d).clone()
+
+
+class FrozenRunner:
+    """Repeated forward runs with one timestep list on one grid handle (the
+    captured graph is reused across runs): run(W0) -> final conserved state."""
+
+    def __init__(self, W_like: torch.Tensor, dx: float, dy: float, bc, dts, potential=None):
+        self.g = Grid(W_like.contiguous(), dx, dy, bc)
+        if potential is not None:
+            self.g.set_potential(*potential)
+        self.dts = torch.as_tensor(dts, dtype=torch.float64).to(W_like.device).contiguous()
+        self.W = torch.empty_like(W_like)
+
+    def run(self, W0: torch.Tensor) -> torch.Tensor:
+        self.W.copy_(W0)
+        self.g.set_state(self.W)
+        return self.g.run_dts(self.dts)

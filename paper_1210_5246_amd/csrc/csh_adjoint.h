@@ -182,7 +182,7 @@ CSH_HD void face_states_vjp(const P& W0, const P& Wl, const P& Wr, const P& Wm, 
                             const Faces<double>& fb, P& W0b, P& Wlb, P& Wrb, P& Wmb, P& Wpb)
 {
     // ---- forward recompute ----
-    const double ir = 1.0 / W0.r;
+    const double ir = rcp(W0.r);
     const E ex = eig_x(W0, ir);
     const P dlx = sub(W0, Wl), drx = sub(Wr, W0);
     const P dxm = limited_slope(W0, ex, dlx, drx);
@@ -441,7 +441,7 @@ CSH_HD void faces_cell(const AdjArgs& a, int i, int j)
     const P W0 = prim_at(a, i, j, TWOD);
     const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
     const P Wm = TWOD ? prim_at(a, i, j - 1, TWOD) : W0, Wp = TWOD ? prim_at(a, i, j + 1, TWOD) : W0;
-    const Faces<double> f = face_states<double, TWOD>(W0, Wl, Wr, Wm, Wp, kx, ky);
+    const Faces<double> f = face_states<double, TWOD>(W0, rcp(W0.r), Wl, Wr, Wm, Wp, kx, ky);
     const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
     store_p(a.FS, ne, XHI, e, f.xhi);
     store_p(a.FS, ne, XLO, e, f.xlo);

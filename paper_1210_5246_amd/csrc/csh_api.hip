@@ -25,9 +25,9 @@ struct csh_grid {
     int ty = 32;                    // rows per wavefront segment
     double* adj_ws = nullptr;       // adjoint workspace, allocated on first use
     size_t adj_ws_n = 0;
-    // cached graph of csh_run_cfl
+    // cached graph of csh_run_cfl / csh_run_dts
     hipGraphExec_t exec = nullptr;
-    int g_nsteps = -1;
+    int g_mode = -1, g_nsteps = -1;
     double g_cfl = 0, g_tend = 0;
     const void *g_U = nullptr, *g_W = nullptr, *g_log = nullptr;
 };
@@ -72,9 +72,10 @@ csh::StepArgs<T> base_args(const csh_grid* h)
 
 template <typename T>
 hipError_t enqueue_step(csh_grid* h, const void* U, void* Un, int dev_dt, double dt, double cfl,
-                        double t_end, double* dt_log, hipStream_t s)
+                        double t_end, double* dt_log, hipStream_t s, const double* dt_in = nullptr)
 {
     auto a = base_args<T>(h);
+    a.dt_in = dt_in;
     a.U = static_cast<const T*>(U);
     a.Unew = static_cast<T*>(Un);
     a.dev_dt = dev_dt;
@@ -122,6 +123,7 @@ void drop_graph(csh_grid* h)
     if (h->exec) (void)hipGraphExecDestroy(h->exec);
     h->exec = nullptr;
     h->g_nsteps = -1;
+    h->g_mode = -1;
 }
 
 }  // namespace
@@ -138,7 +140,8 @@ extern "C" int csh_init_state(csh_grid** out, int nx, int ny, double dx, double 
     if (!out) return csh_fail(CSH_ERR_ARG, "h is NULL");
     *out = nullptr;
     if (nx < 1 || ny < 1) return csh_fail(CSH_ERR_ARG, "nx and ny must be >= 1");
-    if ((long long)nx * ny > (1LL << 31)) return csh_fail(CSH_ERR_ARG, "grid larger than 2^31 cells");
+    if ((long long)nx * ny * (dtype == CSH_F32 ? 4 : 8) >= (1LL << 32))
+        return csh_fail(CSH_ERR_ARG, "one plane of the state must be smaller than 4 GiB");
     if (!(dx > 0) || (ny > 1 && !(dy > 0))) return csh_fail(CSH_ERR_ARG, "dx, dy must be > 0");
     if ((bc_x != CSH_BC_PERIODIC && bc_x != CSH_BC_OUTFLOW) || (bc_y != CSH_BC_PERIODIC && bc_y != CSH_BC_OUTFLOW))
         return csh_fail(CSH_ERR_ARG, "bad boundary condition");
@@ -174,6 +177,22 @@ extern "C" int csh_init_state(csh_grid** out, int nx, int ny, double dx, double 
     if (e != hipSuccess) return cleanup(csh_fail(CSH_ERR_HIP, std::string("init: ") + hipGetErrorString(e)));
     *out = h;
     if (flag) return csh_fail(CSH_ERR_NONPHYSICAL, "initial state not physical");
+    return CSH_OK;
+}
+
+extern "C" int csh_set_state(csh_grid* h, const void* W, void* U)
+{
+    if (!h || !W || !U) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    const int64_t n = (int64_t)h->nx * h->ny;
+    hipError_t e = hipMemsetAsync(h->flag, 0, sizeof(int), h->stream);
+    if (e == hipSuccess)
+        e = h->dtype == CSH_F64 ? csh::launch_init<double>(static_cast<const double*>(W), static_cast<double*>(U), n, h->flag, h->stream)
+                                : csh::launch_init<float>(static_cast<const float*>(W), static_cast<float*>(U), n, h->flag, h->stream);
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("set_state: ") + hipGetErrorString(e));
+    if (flag) return csh_fail(CSH_ERR_NONPHYSICAL, "state not physical");
     return CSH_OK;
 }
 
@@ -242,7 +261,7 @@ extern "C" int csh_fluxes(csh_grid* h, double dt, const void* U, void* Fx, void*
 namespace {
 
 hipError_t enqueue_run(csh_grid* h, int nsteps, double cfl, double t_end, void* U, void* Uw, double* dt_log,
-                       hipStream_t s)
+                       const double* dts, hipStream_t s)
 {
     h->phase = 0;
     hipError_t e = enqueue_maxspeed(h, U, s);  // rate of the initial state into slot 0, t = 0
@@ -250,8 +269,10 @@ hipError_t enqueue_run(csh_grid* h, int nsteps, double cfl, double t_end, void* 
         void* in = (k % 2 == 0) ? U : Uw;
         void* outp = (k % 2 == 0) ? Uw : U;
         double* lg = dt_log ? dt_log + k : nullptr;
-        e = h->dtype == CSH_F64 ? enqueue_step<double>(h, in, outp, 1, 0, cfl, t_end, lg, s)
-                                : enqueue_step<float>(h, in, outp, 1, 0, cfl, t_end, lg, s);
+        const double* di = dts ? dts + k : nullptr;
+        const int dev = dts ? 0 : 1;
+        e = h->dtype == CSH_F64 ? enqueue_step<double>(h, in, outp, dev, 0, cfl, t_end, lg, s, di)
+                                : enqueue_step<float>(h, in, outp, dev, 0, cfl, t_end, lg, s, di);
     }
     if (e == hipSuccess && nsteps % 2 == 1) {
         const int64_t n = 6LL * h->nx * h->ny;
@@ -259,6 +280,42 @@ hipError_t enqueue_run(csh_grid* h, int nsteps, double cfl, double t_end, void* 
                                 : csh::launch_copy<float>(static_cast<float*>(Uw), static_cast<float*>(U), n, s);
     }
     return e;
+}
+
+// record (once per distinct argument set) and replay the graph of a run
+int run_graph(csh_grid* h, int mode, int nsteps, double cfl, double t_end, void* U, void* U_work,
+              const void* lg)
+{
+    const bool same = h->exec && h->g_mode == mode && h->g_nsteps == nsteps && h->g_cfl == cfl &&
+                      h->g_tend == t_end && h->g_U == U && h->g_W == U_work && h->g_log == lg;
+    if (!same) {
+        drop_graph(h);
+        hipGraph_t g = nullptr;
+        CSH_HIP(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+        hipError_t e = mode == 0 ? enqueue_run(h, nsteps, cfl, t_end, U, U_work, (double*)lg, nullptr, h->capture)
+                                 : enqueue_run(h, nsteps, 1.0, 0.0, U, U_work, nullptr, (const double*)lg, h->capture);
+        hipError_t e2 = hipStreamEndCapture(h->capture, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return csh_fail(CSH_ERR_HIP, std::string("run capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            h->exec = nullptr;
+            return csh_fail(CSH_ERR_HIP, std::string("run instantiate: ") + hipGetErrorString(e));
+        }
+        h->g_mode = mode;
+        h->g_nsteps = nsteps;
+        h->g_cfl = cfl;
+        h->g_tend = t_end;
+        h->g_U = U;
+        h->g_W = U_work;
+        h->g_log = lg;
+    }
+    CSH_HIP(hipGraphLaunch(h->exec, h->stream));
+    h->phase = nsteps % 3;
+    return CSH_OK;
 }
 
 }  // namespace
@@ -270,34 +327,16 @@ extern "C" int csh_run_cfl(csh_grid* h, int nsteps, double cfl, double t_end, vo
     if (U == U_work) return csh_fail(CSH_ERR_ARG, "U and U_work must be distinct");
     if (nsteps < 0 || !(cfl > 0)) return csh_fail(CSH_ERR_ARG, "nsteps >= 0 and cfl > 0 required");
     if (nsteps == 0) return CSH_OK;
-    const bool same = h->exec && h->g_nsteps == nsteps && h->g_cfl == cfl && h->g_tend == t_end &&
-                      h->g_U == U && h->g_W == U_work && h->g_log == dt_log;
-    if (!same) {
-        drop_graph(h);
-        hipGraph_t g = nullptr;
-        CSH_HIP(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_run(h, nsteps, cfl, t_end, U, U_work, dt_log, h->capture);
-        hipError_t e2 = hipStreamEndCapture(h->capture, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return csh_fail(CSH_ERR_HIP, std::string("run_cfl capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
-        }
-        e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            h->exec = nullptr;
-            return csh_fail(CSH_ERR_HIP, std::string("run_cfl instantiate: ") + hipGetErrorString(e));
-        }
-        h->g_nsteps = nsteps;
-        h->g_cfl = cfl;
-        h->g_tend = t_end;
-        h->g_U = U;
-        h->g_W = U_work;
-        h->g_log = dt_log;
-    }
-    CSH_HIP(hipGraphLaunch(h->exec, h->stream));
-    h->phase = nsteps % 3;
-    return CSH_OK;
+    return run_graph(h, 0, nsteps, cfl, t_end, U, U_work, dt_log);
+}
+
+extern "C" int csh_run_dts(csh_grid* h, int nsteps, const double* dts, void* U, void* U_work)
+{
+    if (!h || !U || !U_work || (nsteps > 0 && !dts)) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (U == U_work) return csh_fail(CSH_ERR_ARG, "U and U_work must be distinct");
+    if (nsteps < 0) return csh_fail(CSH_ERR_ARG, "nsteps >= 0 required");
+    if (nsteps == 0) return CSH_OK;
+    return run_graph(h, 1, nsteps, 0.0, 0.0, U, U_work, dts);
 }
 
 extern "C" int csh_destroy(csh_grid* h)

@@ -31,6 +31,46 @@
 
 namespace csh {
 
+// Reciprocal and reciprocal square root from the hardware approximations plus
+// one Newton step.  gfx950's FP64 v_rcp/v_rsq are accurate to ~5e-8 relative;
+// one step brings them to ~4e-15, well inside the scheme's parity tolerance,
+// at about half the instructions of the IEEE-exact sequences.  FP32 uses the
+// single-precision instructions (~1 ulp).  On the host (tests) they are exact.
+CSH_HD double rcp(double x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(fma(-x, r, 1.0), r, r);
+#else
+    return 1.0 / x;
+#endif
+}
+CSH_HD float rcp(float x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+CSH_HD double rsqrt(double x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    const double y = __builtin_amdgcn_rsq(x);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+CSH_HD float rsqrt(float x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+
 template <typename T>
 struct Prim {
     T r, u, v, pxx, pxy, pyy;
@@ -67,11 +107,16 @@ CSH_HD Prim<T> sub(const Prim<T>& a, const Prim<T>& b)
 
 // Sec. 2: E_ij = P_ij + rho u_i u_j
 template <typename T>
-CSH_HD Prim<T> to_prim(const Cons<T>& U)
+CSH_HD Prim<T> to_prim(const Cons<T>& U, T ir)
 {
-    const T ir = T(1) / U.r;
     const T u = U.mx * ir, v = U.my * ir;
     return {U.r, u, v, U.exx - U.mx * u, U.exy - U.mx * v, U.eyy - U.my * v};
+}
+
+template <typename T>
+CSH_HD Prim<T> to_prim(const Cons<T>& U)
+{
+    return to_prim(U, rcp(U.r));
 }
 
 template <typename T>
@@ -107,11 +152,13 @@ template <typename T>
 CSH_HD Eig<T> eig_x(const Prim<T>& w, T ir)
 {
     Eig<T> e;
-    e.c = sqrt(w.pxx * ir);
+    const T t = w.pxx * ir;
+    const T y = rsqrt(t);                 // 1 / c
+    e.c = t * y;
     e.a = T(1.7320508075688772935) * e.c;  // sqrt(3) c
-    e.h2c = T(0.5) / e.c;
-    e.h2a = T(0.28867513459481288225) / e.c;  // 1 / (2 sqrt(3) c)
-    e.ip = T(1) / w.pxx;
+    e.h2c = T(0.5) * y;
+    e.h2a = T(0.28867513459481288225) * y;  // 1 / (2 sqrt(3) c)
+    e.ip = rcp(w.pxx);
     e.q = w.pxy * e.ip;
     return e;
 }
@@ -215,7 +262,8 @@ CSH_HD Face<T> make_face_x(const Prim<T>& w)
     Face<T> f;
     f.w = w;
     f.U = to_cons(w);
-    f.a = sqrt(T(3) * w.pxx / w.r);
+    const T t = T(3) * w.pxx;
+    f.a = t * rsqrt(t * w.r);  // sqrt(3 Pxx / rho)
     return f;
 }
 
@@ -225,7 +273,7 @@ CSH_HD Cons<T> hll_x(const Face<T>& L, const Face<T>& R)
 {
     const T sl = fmin(fmin(L.w.u - L.a, R.w.u - R.a), T(0));
     const T sr = fmax(fmax(L.w.u + L.a, R.w.u + R.a), T(0));
-    const T inv = T(1) / (sr - sl);
+    const T inv = rcp(sr - sl);
     const T slr = sl * sr;
     const Cons<T> FL = flux_x(L.w, L.U), FR = flux_x(R.w, R.U);
     Cons<T> F;
@@ -254,10 +302,9 @@ struct Faces {
 };
 
 template <typename T, bool TWOD>
-CSH_HD Faces<T> face_states(const Prim<T>& W0, const Prim<T>& Wl, const Prim<T>& Wr, const Prim<T>& Wm,
+CSH_HD Faces<T> face_states(const Prim<T>& W0, T ir, const Prim<T>& Wl, const Prim<T>& Wr, const Prim<T>& Wm,
                             const Prim<T>& Wp, T kx, T ky)
 {
-    const T ir = T(1) / W0.r;
     const Eig<T> ex = eig_x(W0, ir);
     const Prim<T> dxm = limited_slope(W0, ex, sub(W0, Wl), sub(Wr, W0));
     Prim<T> base = axpy(-kx, jac_x(W0, ir, dxm), W0);
@@ -285,9 +332,13 @@ CSH_HD Faces<T> face_states(const Prim<T>& W0, const Prim<T>& Wl, const Prim<T>&
 template <typename T, bool TWOD>
 CSH_HD double signal_rate(const Prim<T>& w, double idx, double idy)
 {
-    const double ir = 1.0 / double(w.r);
-    double s = (fabs(double(w.u)) + sqrt(3.0 * double(w.pxx) * ir)) * idx;
-    if (TWOD) s += (fabs(double(w.v)) + sqrt(3.0 * double(w.pyy) * ir)) * idy;
+    const double ir = rcp(double(w.r));
+    const double tx = 3.0 * double(w.pxx) * ir;
+    double s = (fabs(double(w.u)) + tx * rsqrt(tx)) * idx;
+    if (TWOD) {
+        const double ty = 3.0 * double(w.pyy) * ir;
+        s += (fabs(double(w.v)) + ty * rsqrt(ty)) * idy;
+    }
     return s;
 }
 
@@ -296,9 +347,8 @@ template <typename T>
 CSH_HD bool physical(const Prim<T>& w)
 {
     const bool pd = w.r > T(0) && w.pxx > T(0) && w.pyy > T(0) && w.pxx * w.pyy - w.pxy * w.pxy > T(0);
-    const bool fin = isfinite(w.r) && isfinite(w.u) && isfinite(w.v) && isfinite(w.pxx) &&
-                     isfinite(w.pxy) && isfinite(w.pyy);
-    return pd && fin;
+    // a NaN or infinity in any component makes the sum NaN or infinite
+    return pd && isfinite(w.r + w.u + w.v + w.pxx + w.pxy + w.pyy);
 }
 
 // ---- wavefront primitives --------------------------------------------------------------------
@@ -356,8 +406,9 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double 
 template <typename T>
 __device__ __forceinline__ Cons<T> flux_1d(const Cons<T>& U0, T kx)
 {
-    const Prim<T> W0 = to_prim(U0);
-    const Faces<T> f = face_states<T, false>(W0, lane_shift(W0, -1), lane_shift(W0, +1), W0, W0, kx, T(0));
+    const T ir = rcp(U0.r);
+    const Prim<T> W0 = to_prim(U0, ir);
+    const Faces<T> f = face_states<T, false>(W0, ir, lane_shift(W0, -1), lane_shift(W0, +1), W0, W0, kx, T(0));
     return hll_x(make_face_x(f.xhi), lane_shift(make_face_x(f.xlo), +1));
 }
 
@@ -387,6 +438,44 @@ CSH_HD void store_cons(T* __restrict__ U, size_t plane, size_t c, const Cons<T>&
     U[4 * plane + c] = v.exy;
     U[5 * plane + c] = v.eyy;
 }
+
+// The six planes of a state as wave-uniform base pointers, addressed with a
+// 32-bit byte offset (planes are limited to 4 GiB at init), so each access is
+// a scalar base plus one vector offset.
+template <typename T>
+struct Planes {
+    const char* b[6];
+    CSH_HD Planes(const T* U, size_t plane)
+    {
+        for (int k = 0; k < 6; ++k) b[k] = reinterpret_cast<const char*>(U + k * plane);
+    }
+    CSH_HD Cons<T> load(unsigned cell) const
+    {
+        const unsigned o = cell * (unsigned)sizeof(T);
+        return {*reinterpret_cast<const T*>(b[0] + o), *reinterpret_cast<const T*>(b[1] + o),
+                *reinterpret_cast<const T*>(b[2] + o), *reinterpret_cast<const T*>(b[3] + o),
+                *reinterpret_cast<const T*>(b[4] + o), *reinterpret_cast<const T*>(b[5] + o)};
+    }
+};
+
+template <typename T>
+struct OutPlanes {
+    char* b[6];
+    CSH_HD OutPlanes(T* U, size_t plane)
+    {
+        for (int k = 0; k < 6; ++k) b[k] = reinterpret_cast<char*>(U + k * plane);
+    }
+    CSH_HD void store(unsigned cell, const Cons<T>& v) const
+    {
+        const unsigned o = cell * (unsigned)sizeof(T);
+        *reinterpret_cast<T*>(b[0] + o) = v.r;
+        *reinterpret_cast<T*>(b[1] + o) = v.mx;
+        *reinterpret_cast<T*>(b[2] + o) = v.my;
+        *reinterpret_cast<T*>(b[3] + o) = v.exx;
+        *reinterpret_cast<T*>(b[4] + o) = v.exy;
+        *reinterpret_cast<T*>(b[5] + o) = v.eyy;
+    }
+};
 
 CSH_HD int map_index(int i, int n, int bc)
 {

@@ -24,7 +24,7 @@ __device__ __forceinline__ double step_dt(const StepArgs<T>& p, double* t_now)
     const Slot& sl = p.slots[p.s_in];
     const double t = sl.t;
     *t_now = t;
-    if (!p.dev_dt) return p.dt;
+    if (!p.dev_dt) return p.dt_in ? *p.dt_in : p.dt;
     const double s = __longlong_as_double((long long)sl.s_bits);
     double dt = p.cfl / s;
     if (p.t_end > 0.0) {
@@ -42,7 +42,7 @@ __device__ __forceinline__ void kick(Cons<T>& U, const StepArgs<T>& p, double dt
     if (p.vc2 == 0.0) return;
     const double x = p.x0 + (i + 0.5) * p.dx;
     const double y = twod ? p.y0 + (j + 0.5) * p.dy : 0.0;
-    const double f = -p.vc2 / (x * x + y * y + p.rc2);
+    const double f = -p.vc2 * rcp(x * x + y * y + p.rc2);
     const T ax = T(f * x), ay = T(f * y);
     const T h = T(dt);
     const T mx = U.mx, my = U.my;
@@ -105,58 +105,70 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
     } else {
         const T ky = T(dt / (2.0 * p.dy)), cy = T(dt / p.dy);
         const int y0 = sy * p.ty, y1 = min(y0 + p.ty, p.ny);
+        const Planes<T> in(p.U, plane);
+        const OutPlanes<T> out(p.Unew, plane);
         auto load_row = [&](int r) -> Cons<T> {
             const int gr = map_index(r, p.ny, p.bcy);
-            return load_cons(p.U, plane, (size_t)gr * p.nx + gc);
+            return in.load((unsigned)(gr * p.nx + gc));
         };
+        // row window: primitive states of rows r-1, r, r+1 (and 1/rho of r, r+1),
+        // conserved states of rows r, r+1
         Cons<T> U0 = load_row(y0 - 1), Up = load_row(y0);
-        Prim<T> Wm = to_prim(load_row(y0 - 2)), W0 = to_prim(U0), Wp = to_prim(Up);
-        Face<T> yhi_prev;   // high y-face state of the cell below, in swapped (normal = x) form
-        Cons<T> F_prev;     // F(c + 1/2, r - 1)
-        Cons<T> G_prev;     // G(c, r - 3/2)
-        Cons<T> Uc_prev;    // U^n(c, r - 1)
+        const Cons<T> Um = load_row(y0 - 2);
+        T ir0 = rcp(U0.r), irp = rcp(Up.r);
+        Prim<T> Wm = to_prim(Um), W0 = to_prim(U0, ir0), Wp = to_prim(Up, irp);
+        Prim<T> yhi_prev{};  // high y-face state of the cell below (primitive, axes not exchanged)
+        Cons<T> acc{};       // update of the cell below, all but its high y-face flux
 
+#pragma unroll 3
         for (int r = y0 - 1; r <= y1; ++r) {
             const Cons<T> Unext = (r + 2 <= y1 + 1) ? load_row(r + 2) : Up;
 
             // face states of (c, r): x neighbours from the adjacent lanes, y from the row window
-            const Faces<T> fs = face_states<T, true>(W0, lane_shift(W0, -1), lane_shift(W0, +1), Wm, Wp, kx, ky);
-            const Face<T> xhi = make_face_x(fs.xhi);
-            const Face<T> xlo = make_face_x(fs.xlo);
-            const Face<T> yhi = make_face_x(swap(fs.yhi));
-            const Face<T> ylo = make_face_x(swap(fs.ylo));
+            const Faces<T> fs =
+                face_states<T, true>(W0, ir0, lane_shift(W0, -1), lane_shift(W0, +1), Wm, Wp, kx, ky);
 
-            const Cons<T> F = hll_x(xhi, lane_shift(xlo, +1));  // x face c + 1/2, row r
-            Cons<T> G{};                                        // y face r - 1/2
-            if (r >= y0) G = swap(hll_x(yhi_prev, ylo));
-
-            if constexpr (FLUXES) {
-                if (r >= y0 && r < y1 && lane >= 1 && lane <= 1 + kStrip && c >= -1 && c <= p.nx - 1)
-                    store_face(p.Fx, (size_t)(p.nx + 1) * p.ny, (size_t)r * (p.nx + 1) + (c + 1), F);
-                if (r >= y0 && own)
-                    store_face(p.Fy, (size_t)p.nx * (p.ny + 1), (size_t)r * p.nx + c, G);
-            } else {
-                if (r >= y0 + 1) {  // update cell (c, r - 1)
-                    const Cons<T> Fm = lane_shift(F_prev, -1);
-                    Cons<T> Un = update(update(Uc_prev, cx, F_prev, Fm), cy, G, G_prev);
+            if (r >= y0) {
+                // y face r - 1/2 between the cell below (its high state) and this cell (low state)
+                const Cons<T> G = swap(hll_x(make_face_x(swap(yhi_prev)), make_face_x(swap(fs.ylo))));
+                if constexpr (FLUXES) {
+                    if (own) store_face(p.Fy, (size_t)p.nx * (p.ny + 1), (size_t)r * p.nx + c, G);
+                } else if (r > y0) {  // finish cell (c, r - 1)
+                    Cons<T> Un = {acc.r - cy * G.r,     acc.mx - cy * G.mx,   acc.my - cy * G.my,
+                                  acc.exx - cy * G.exx, acc.exy - cy * G.exy, acc.eyy - cy * G.eyy};
                     kick(Un, p, dt, c, r - 1, true);
                     if (own) {
-                        store_cons(p.Unew, plane, (size_t)(r - 1) * p.nx + c, Un);
+                        out.store((unsigned)((r - 1) * p.nx + c), Un);
                         const Prim<T> wn = to_prim(Un);
                         smax = fmax(smax, signal_rate<T, true>(wn, idx, idy));
                         bad = bad || !physical(wn);
                     }
                 }
+                if (r < y1) {
+                    // x faces of row r, then start the update of (c, r) with its low y face
+                    const Cons<T> F = hll_x(make_face_x(fs.xhi), make_face_x(lane_shift(fs.xlo, +1)));
+                    if constexpr (FLUXES) {
+                        if (lane >= 1 && lane <= 1 + kStrip && c >= -1 && c <= p.nx - 1)
+                            store_face(p.Fx, (size_t)(p.nx + 1) * p.ny, (size_t)r * (p.nx + 1) + (c + 1), F);
+                    } else {
+                        const Cons<T> Fm = lane_shift(F, -1);
+                        acc = {U0.r - cx * (F.r - Fm.r) + cy * G.r,
+                               U0.mx - cx * (F.mx - Fm.mx) + cy * G.mx,
+                               U0.my - cx * (F.my - Fm.my) + cy * G.my,
+                               U0.exx - cx * (F.exx - Fm.exx) + cy * G.exx,
+                               U0.exy - cx * (F.exy - Fm.exy) + cy * G.exy,
+                               U0.eyy - cx * (F.eyy - Fm.eyy) + cy * G.eyy};
+                    }
+                }
             }
-            F_prev = F;
-            G_prev = G;
-            yhi_prev = yhi;
-            Uc_prev = U0;
+            yhi_prev = fs.yhi;
             Wm = W0;
             W0 = Wp;
+            ir0 = irp;
             U0 = Up;
             Up = Unext;
-            Wp = to_prim(Unext);
+            irp = rcp(Unext.r);
+            Wp = to_prim(Unext, irp);
         }
         if constexpr (FLUXES) return;
     }

@@ -33,6 +33,7 @@ struct StepArgs {
     Slot* slots;
     int s_in, s_out, s_reset;
     double* dt_log;          // if set, receives the timestep used
+    const double* dt_in;     // if set (and dev_dt == 0), the timestep is read from here
     double vc2, rc2, x0, y0; // external flat-rotation-curve potential (vc2 == 0: none)
     int* flag;               // set to 1 if an output cell is not physical
 };

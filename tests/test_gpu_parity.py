@@ -137,10 +137,14 @@ def test_host_dt_steps_equal_device_cfl_run():
     g1 = gpu_grid(w)
     U = g1.U.clone()
     dts = []
+    s = g1.max_signal_speed(U)           # the device run also starts from this kernel
     for _ in range(12):
-        dt = 0.8 / g1.max_signal_speed(U)
+        dt = 0.8 / s
         U = g1.step(dt, U)
         dts.append(dt)
+        s = g1.last_signal_speed()       # the rate the step fused, as the device run uses
+        # the standalone reduction may contract differently: an ulp apart at most
+        assert g1.max_signal_speed(U) == pytest.approx(s, rel=1e-15)
     g2 = gpu_grid(w)
     dts2 = g2.run_cfl(12, 0.8).cpu().numpy()
     np.testing.assert_allclose(dts2, dts, rtol=1e-15)
@@ -222,3 +226,19 @@ def test_fp32_twin_close_to_fp64():
     err = max_rel_error(g.U.double().cpu().numpy(), ref)
     say("fp32 max rel error after 5 steps:", err)
     assert err < 1e-3
+
+
+def test_run_dts_replays_run_cfl_bitwise_and_set_state():
+    w = wl.periodic(200, 27, 9)
+    say("run_dts replay")
+    g = gpu_grid(w)
+    W = torch.from_numpy(w.W).to(DEV)
+    dts = g.run_cfl(9, 0.8).clone()
+    ref = g.U.clone()
+    g.set_state(W)                      # back to the initial state on the same handle
+    g.run_dts(dts)
+    assert torch.equal(g.U, ref)
+    W2 = W.clone()
+    W2[3, 4, 5] = -1.0
+    with pytest.raises(csh.NonPhysicalState):
+        g.set_state(W2)
