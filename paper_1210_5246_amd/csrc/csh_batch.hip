@@ -88,7 +88,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs a)
                 const int c = base - 2 + lane;
                 const Cons<double> U0 = load_cons<double>(A, plane, (size_t)clamp_cell(c, n));
                 const Cons<double> F = flux_1d(U0, kx);
-                const Cons<double> Un = update(U0, cx, F, lane_shift(F, -1));
+                const Cons<double> Un = update(U0, cx, F, lane_shift<-1>(F));
                 if (lane >= 2 && lane < 2 + kStrip && c < n) {
                     store_cons(B, plane, (size_t)c, Un);
                     const Prim<double> wn = to_prim(Un);

@@ -353,35 +353,36 @@ CSH_HD bool physical(const Prim<T>& w)
 
 // ---- wavefront primitives --------------------------------------------------------------------
 
-// value held by lane (lane + delta), delta = +-1; the two edge lanes receive the
-// opposite edge's value, which the callers never use (edge lanes are halo)
-__device__ __forceinline__ double lane_shift(double x, int delta)
+// Value held by lane (lane + D), D = +1 or -1, by a DPP whole-wavefront shift
+// (wave_shl:1 / wave_shr:1; lane layout checked on gfx950).  The lane at the
+// end the shift comes from receives 0; callers never use it (it is halo).
+template <int D>
+__device__ __forceinline__ double lane_shift(double x)
 {
-    return __shfl(x, (int)(threadIdx.x & 63) + delta, 64);
+    constexpr int ctrl = D > 0 ? 0x130 : 0x138;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float lane_shift(float x, int delta)
+template <int D>
+__device__ __forceinline__ float lane_shift(float x)
 {
-    return __shfl(x, (int)(threadIdx.x & 63) + delta, 64);
-}
-
-template <typename T>
-__device__ __forceinline__ Prim<T> lane_shift(const Prim<T>& w, int d)
-{
-    return {lane_shift(w.r, d), lane_shift(w.u, d), lane_shift(w.v, d),
-            lane_shift(w.pxx, d), lane_shift(w.pxy, d), lane_shift(w.pyy, d)};
-}
-
-template <typename T>
-__device__ __forceinline__ Cons<T> lane_shift(const Cons<T>& U, int d)
-{
-    return {lane_shift(U.r, d), lane_shift(U.mx, d), lane_shift(U.my, d),
-            lane_shift(U.exx, d), lane_shift(U.exy, d), lane_shift(U.eyy, d)};
+    constexpr int ctrl = D > 0 ? 0x130 : 0x138;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false));
 }
 
-template <typename T>
-__device__ __forceinline__ Face<T> lane_shift(const Face<T>& f, int d)
+template <int D, typename T>
+__device__ __forceinline__ Prim<T> lane_shift(const Prim<T>& w)
 {
-    return {lane_shift(f.w, d), lane_shift(f.U, d), lane_shift(f.a, d)};
+    return {lane_shift<D>(w.r), lane_shift<D>(w.u), lane_shift<D>(w.v),
+            lane_shift<D>(w.pxx), lane_shift<D>(w.pxy), lane_shift<D>(w.pyy)};
+}
+
+template <int D, typename T>
+__device__ __forceinline__ Cons<T> lane_shift(const Cons<T>& U)
+{
+    return {lane_shift<D>(U.r), lane_shift<D>(U.mx), lane_shift<D>(U.my),
+            lane_shift<D>(U.exx), lane_shift<D>(U.exy), lane_shift<D>(U.eyy)};
 }
 
 // max over the wavefront
@@ -408,8 +409,8 @@ __device__ __forceinline__ Cons<T> flux_1d(const Cons<T>& U0, T kx)
 {
     const T ir = rcp(U0.r);
     const Prim<T> W0 = to_prim(U0, ir);
-    const Faces<T> f = face_states<T, false>(W0, ir, lane_shift(W0, -1), lane_shift(W0, +1), W0, W0, kx, T(0));
-    return hll_x(make_face_x(f.xhi), lane_shift(make_face_x(f.xlo), +1));
+    const Faces<T> f = face_states<T, false>(W0, ir, lane_shift<-1>(W0), lane_shift<+1>(W0), W0, W0, kx, T(0));
+    return hll_x(make_face_x(f.xhi), make_face_x(lane_shift<+1>(f.xlo)));
 }
 
 template <typename T>

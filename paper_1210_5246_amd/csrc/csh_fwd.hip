@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
                 store_face(p.Fx, (size_t)(p.nx + 1), (size_t)(c + 1), F);
             return;
         }
-        const Cons<T> Fm = lane_shift(F, -1);
+        const Cons<T> Fm = lane_shift<-1>(F);
         Cons<T> Un = update(U0, cx, F, Fm);
         kick(Un, p, dt, c, 0, false);
         if (own) {
@@ -111,22 +111,22 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
             const int gr = map_index(r, p.ny, p.bcy);
             return in.load((unsigned)(gr * p.nx + gc));
         };
-        // row window: primitive states of rows r-1, r, r+1 (and 1/rho of r, r+1),
-        // conserved states of rows r, r+1
-        Cons<T> U0 = load_row(y0 - 1), Up = load_row(y0);
-        const Cons<T> Um = load_row(y0 - 2);
-        T ir0 = rcp(U0.r), irp = rcp(Up.r);
-        Prim<T> Wm = to_prim(Um), W0 = to_prim(U0, ir0), Wp = to_prim(Up, irp);
+        // Row window in three rotating register sets: the set holding row r-1
+        // is refilled with row r+2, so the window advances without moves.
+        Cons<T> Ua = load_row(y0 - 2), Ub = load_row(y0 - 1), Uc = load_row(y0);
+        T ia = rcp(Ua.r), ib = rcp(Ub.r), ic = rcp(Uc.r);
+        Prim<T> Wa = to_prim(Ua, ia), Wb = to_prim(Ub, ib), Wc = to_prim(Uc, ic);
         Prim<T> yhi_prev{};  // high y-face state of the cell below (primitive, axes not exchanged)
         Cons<T> acc{};       // update of the cell below, all but its high y-face flux
 
-#pragma unroll 3
-        for (int r = y0 - 1; r <= y1; ++r) {
-            const Cons<T> Unext = (r + 2 <= y1 + 1) ? load_row(r + 2) : Up;
+        // one row: (Um, Wm) row r-1 (refilled with row r+2), (U0, W0, ir0) row r, Wp row r+1
+        auto row = [&](int r, Cons<T>& Um, Prim<T>& Wm, T& irm, const Cons<T>& U0, const Prim<T>& W0, T ir0,
+                       const Prim<T>& Wp) {
+            const Cons<T> Unext = (r + 2 <= y1 + 1) ? load_row(r + 2) : U0;
 
             // face states of (c, r): x neighbours from the adjacent lanes, y from the row window
             const Faces<T> fs =
-                face_states<T, true>(W0, ir0, lane_shift(W0, -1), lane_shift(W0, +1), Wm, Wp, kx, ky);
+                face_states<T, true>(W0, ir0, lane_shift<-1>(W0), lane_shift<+1>(W0), Wm, Wp, kx, ky);
 
             if (r >= y0) {
                 // y face r - 1/2 between the cell below (its high state) and this cell (low state)
@@ -146,12 +146,12 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
                 }
                 if (r < y1) {
                     // x faces of row r, then start the update of (c, r) with its low y face
-                    const Cons<T> F = hll_x(make_face_x(fs.xhi), make_face_x(lane_shift(fs.xlo, +1)));
+                    const Cons<T> F = hll_x(make_face_x(fs.xhi), make_face_x(lane_shift<+1>(fs.xlo)));
                     if constexpr (FLUXES) {
                         if (lane >= 1 && lane <= 1 + kStrip && c >= -1 && c <= p.nx - 1)
                             store_face(p.Fx, (size_t)(p.nx + 1) * p.ny, (size_t)r * (p.nx + 1) + (c + 1), F);
                     } else {
-                        const Cons<T> Fm = lane_shift(F, -1);
+                        const Cons<T> Fm = lane_shift<-1>(F);
                         acc = {U0.r - cx * (F.r - Fm.r) + cy * G.r,
                                U0.mx - cx * (F.mx - Fm.mx) + cy * G.mx,
                                U0.my - cx * (F.my - Fm.my) + cy * G.my,
@@ -162,13 +162,17 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
                 }
             }
             yhi_prev = fs.yhi;
-            Wm = W0;
-            W0 = Wp;
-            ir0 = irp;
-            U0 = Up;
-            Up = Unext;
-            irp = rcp(Unext.r);
-            Wp = to_prim(Unext, irp);
+            Um = Unext;  // row r + 2 takes the place of row r - 1
+            irm = rcp(Unext.r);
+            Wm = to_prim(Unext, irm);
+        };
+
+        for (int r = y0 - 1; r <= y1; r += 3) {
+            row(r, Ua, Wa, ia, Ub, Wb, ib, Wc);
+            if (r + 1 > y1) break;
+            row(r + 1, Ub, Wb, ib, Uc, Wc, ic, Wa);
+            if (r + 2 > y1) break;
+            row(r + 2, Uc, Wc, ic, Ua, Wa, ia, Wb);
         }
         if constexpr (FLUXES) return;
     }
