@@ -112,6 +112,8 @@ def lib():
         L.orc_trace.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, _D, _D]
         L.orc_hll.argtypes = [ctypes.c_int, _D, _D, _D]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_kt_flux.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_step_kt.argtypes = [G, ctypes.c_double, _D, _D]
         _lib = L
     return _lib
 
@@ -212,6 +214,21 @@ def step(g: Grid, dt: float, U: np.ndarray) -> np.ndarray:
     return out
 
 
+def kt_flux(direction: int, wl, wr) -> np.ndarray:
+    """Numerical flux of eq. (6) of the Kurganov-Tadmor scheme (u^- = wl, u^+ = wr)."""
+    wl, wr = _vec(wl), _vec(wr); out = np.empty(6)
+    lib().orc_kt_flux(direction, _p(wl), _p(wr), _p(out))
+    return out
+
+
+def step_kt(g: Grid, dt: float, U: np.ndarray) -> np.ndarray:
+    """One step of the Kurganov-Tadmor scheme (Sec. 3.2; readings in cshoracle.c)."""
+    U = _check(g, U); out = np.empty_like(U)
+    if lib().orc_step_kt(ctypes.byref(g.c()), dt, _p(U), _p(out)) != 0:
+        raise ValueError("bad grid")
+    return out
+
+
 def step_cells(g: Grid, dt: float, U: np.ndarray, cells) -> np.ndarray:
     """Updated conserved state of the listed cells (flat index j*nx+i): [len(cells), 6]."""
     U = _check(g, U)
@@ -246,11 +263,12 @@ def physical(g: Grid, U: np.ndarray) -> bool:
 # ---- drivers ---------------------------------------------------------------------------
 
 def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
-            t_end: float | None = None, max_steps: int = 20000):
+            t_end: float | None = None, max_steps: int = 20000, scheme: str = "muscl"):
     """Advance with dt = cfl / s (s from the state at the start of each step).
 
     Stops after ``nsteps`` steps, or when ``t_end`` is reached (the last step is
-    clipped to land on it).  Returns (U, list of dt).
+    clipped to land on it).  ``scheme``: "muscl" (Sec. 3.3) or "kt" (Sec. 3.2).
+    Returns (U, list of dt).
     """
     U = _check(g, U).copy()
     dts, t = [], 0.0
@@ -266,7 +284,7 @@ def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
             raise FloatingPointError(f"timestep {dt} at step {len(dts)}: the state is not physical")
         if t_end is not None and t + dt > t_end:
             dt = t_end - t
-        U = step(g, dt, U)
+        U = step(g, dt, U) if scheme == "muscl" else step_kt(g, dt, U)
         dts.append(dt)
         t += dt
     return U, dts

@@ -679,3 +679,134 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------------- */
+/* Kurganov-Tadmor central scheme (Sec. 3.2, eqs. (5)-(8)).                */
+/* ---------------------------------------------------------------------- */
+/*
+ * Readings (the section leaves them open):
+ *   K1 reconstruction: piecewise-linear in the primitive variables, each
+ *      component limited on its own with the MC limiter of eq. (25) (no
+ *      characteristic projection: the scheme needs no eigenvectors);
+ *   K2 local speed of eq. (7): the spectral radius of dF/dU at the two face
+ *      states, |u_n| + a_n with a_n the directional sound speed of eq. (8),
+ *      gamma = 3;
+ *   K3 time integration: the Runge-Kutta midpoint rule
+ *        U* = U^n + dt/2 L(U^n),  U^{n+1} = U^n + dt L(U*),
+ *      L = -(H_{i+1/2} - H_{i-1/2})/dx - (H_{j+1/2} - H_{j-1/2})/dy (eq. (5),
+ *      unsplit in 2-D), then the external kick as for the other scheme.
+ */
+
+/* Numerical flux of eq. (6) in direction dir from the states on the two sides
+ * of a face: wl = u^- (left), wr = u^+ (right). */
+void orc_kt_flux(int dir, const double wl[NV], const double wr[NV], double flux[NV])
+{
+    double Ul[NV], Ur[NV], Fl[NV], Fr[NV];
+    orc_cons(wl, Ul);
+    orc_cons(wr, Ur);
+    int iv = (dir == 0) ? IU : IV, ip = (dir == 0) ? IXX : IYY;
+    if (dir == 0) {
+        orc_flux_x(Ul, Fl);
+        orc_flux_x(Ur, Fr);
+    } else {
+        orc_flux_y(Ul, Fl);
+        orc_flux_y(Ur, Fr);
+    }
+    double rl = fabs(wl[iv]) + sqrt(3.0 * wl[ip] / wl[IR]);
+    double rr = fabs(wr[iv]) + sqrt(3.0 * wr[ip] / wr[IR]);
+    double a = fmax(rl, rr);
+    for (int m = 0; m < NV; ++m) flux[m] = 0.5 * (Fl[m] + Fr[m]) - 0.5 * a * (Ur[m] - Ul[m]);
+}
+
+/* L(U) on the interior of a padded block (same padding as step_block). */
+static void kt_rhs(const orc_grid *g, int nxi, int nyi, int twod, const double *Wp, double *L)
+{
+    const int px = nxi + 4;
+    const int sx = nxi + 2, sy = twod ? nyi + 2 : 1;
+#define WP(i, j) (Wp + ((size_t)((j) + (twod ? 2 : 0)) * px + (size_t)((i) + 2)) * NV)
+#define SIDX(i, j) (((size_t)((j) + (twod ? 1 : 0)) * sx + (size_t)((i) + 1)) * NV)
+    size_t ns = (size_t)sx * sy * NV;
+    double *sxl = malloc(ns * sizeof(double)), *syl = twod ? malloc(ns * sizeof(double)) : NULL;
+    /* component-wise MC slopes of every cell and its one-cell ring (K1) */
+    #pragma omp parallel for schedule(static)
+    for (int jj = 0; jj < sy; ++jj) {
+        int j = twod ? jj - 1 : 0;
+        for (int i = -1; i <= nxi; ++i) {
+            const double *w = WP(i, j), *wl = WP(i - 1, j), *wr = WP(i + 1, j);
+            size_t s = SIDX(i, j);
+            for (int m = 0; m < NV; ++m)
+                sxl[s + m] = orc_mc(w[m] - wl[m], 0.5 * (wr[m] - wl[m]), wr[m] - w[m]);
+            if (twod) {
+                const double *wd = WP(i, j - 1), *wu = WP(i, j + 1);
+                for (int m = 0; m < NV; ++m)
+                    syl[s + m] = orc_mc(w[m] - wd[m], 0.5 * (wu[m] - wd[m]), wu[m] - w[m]);
+            }
+        }
+    }
+    const double idx = 1.0 / g->dx, idy = twod ? 1.0 / g->dy : 0.0;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < nyi; ++j)
+        for (int i = 0; i < nxi; ++i) {
+            double hp[NV], hm[NV], wl[NV], wr[NV];
+            size_t c = ((size_t)j * nxi + i) * NV;
+            /* x faces: i+1/2 (cells i, i+1) and i-1/2 (cells i-1, i) */
+            for (int m = 0; m < NV; ++m) {
+                wl[m] = WP(i, j)[m] + 0.5 * sxl[SIDX(i, j) + m];
+                wr[m] = WP(i + 1, j)[m] - 0.5 * sxl[SIDX(i + 1, j) + m];
+            }
+            orc_kt_flux(0, wl, wr, hp);
+            for (int m = 0; m < NV; ++m) {
+                wl[m] = WP(i - 1, j)[m] + 0.5 * sxl[SIDX(i - 1, j) + m];
+                wr[m] = WP(i, j)[m] - 0.5 * sxl[SIDX(i, j) + m];
+            }
+            orc_kt_flux(0, wl, wr, hm);
+            for (int m = 0; m < NV; ++m) L[c + m] = -(hp[m] - hm[m]) * idx;
+            if (twod) {
+                for (int m = 0; m < NV; ++m) {
+                    wl[m] = WP(i, j)[m] + 0.5 * syl[SIDX(i, j) + m];
+                    wr[m] = WP(i, j + 1)[m] - 0.5 * syl[SIDX(i, j + 1) + m];
+                }
+                orc_kt_flux(1, wl, wr, hp);
+                for (int m = 0; m < NV; ++m) {
+                    wl[m] = WP(i, j - 1)[m] + 0.5 * syl[SIDX(i, j - 1) + m];
+                    wr[m] = WP(i, j)[m] - 0.5 * syl[SIDX(i, j) + m];
+                }
+                orc_kt_flux(1, wl, wr, hm);
+                for (int m = 0; m < NV; ++m) L[c + m] -= (hp[m] - hm[m]) * idy;
+            }
+        }
+    free(sxl);
+    free(syl);
+#undef WP
+#undef SIDX
+}
+
+/* One step of the KT scheme (readings K1-K3), U -> Unew. */
+int orc_step_kt(const orc_grid *g, double dt, const double *U, double *Unew)
+{
+    if (!grid_ok(g)) return -1;
+    int twod = g->ny > 1;
+    size_t n = (size_t)g->nx * g->ny;
+    double *Us = malloc(n * NV * sizeof(double)), *L = malloc(n * NV * sizeof(double));
+    /* stage 1: U* = U + dt/2 L(U) */
+    double *Wp = padded_prim(g, U, 0, 0, g->nx, g->ny);
+    kt_rhs(g, g->nx, g->ny, twod, Wp, L);
+    free(Wp);
+    for (size_t c = 0; c < n; ++c)
+        for (int m = 0; m < NV; ++m) Us[m * n + c] = U[m * n + c] + 0.5 * dt * L[c * NV + m];
+    /* stage 2: U^{n+1} = U + dt L(U*) */
+    Wp = padded_prim(g, Us, 0, 0, g->nx, g->ny);
+    kt_rhs(g, g->nx, g->ny, twod, Wp, L);
+    free(Wp);
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            size_t c = (size_t)j * g->nx + i;
+            double u[NV];
+            for (int m = 0; m < NV; ++m) u[m] = U[m * n + c] + dt * L[c * NV + m];
+            kick(g, i, j, dt, u);
+            for (int m = 0; m < NV; ++m) Unew[m * n + c] = u[m];
+        }
+    free(Us);
+    free(L);
+    return 0;
+}

@@ -55,4 +55,8 @@ void orc_cons_field(int64_t n, const double *W, double *U);
 void orc_prim_field(int64_t n, const double *U, double *W);
 int orc_num_threads(void);
 
+/* Kurganov-Tadmor central scheme: numerical flux of eq. (6) and one step. */
+void orc_kt_flux(int dir, const double wl[6], const double wr[6], double flux[6]);
+int orc_step_kt(const orc_grid *g, double dt, const double *U, double *Unew);
+
 #endif

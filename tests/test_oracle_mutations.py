@@ -56,6 +56,16 @@ MUTANTS = {
     "bc_outflow": ("if (i < 0) return 0;", "if (i < 0) return 1;"),
     # periodic wrap off by one
     "bc_periodic": ("return (r < 0) ? r + n : r;", "return (r < 0) ? r + n - 1 : r;"),
+    # KT: dissipation with the wrong sign, local speed without |u|, stage
+    # without the 1/2 of the midpoint rule, reconstruction without the limiter
+    "kt_dissipation_sign": ("flux[m] = 0.5 * (Fl[m] + Fr[m]) - 0.5 * a * (Ur[m] - Ul[m]);",
+                            "flux[m] = 0.5 * (Fl[m] + Fr[m]) + 0.5 * a * (Ur[m] - Ul[m]);"),
+    "kt_speed_no_u": ("double rl = fabs(wl[iv]) + sqrt(3.0 * wl[ip] / wl[IR]);",
+                      "double rl = sqrt(3.0 * wl[ip] / wl[IR]);"),
+    "kt_midpoint_half": ("Us[m * n + c] = U[m * n + c] + 0.5 * dt * L[c * NV + m];",
+                         "Us[m * n + c] = U[m * n + c] + dt * L[c * NV + m];"),
+    "kt_unlimited_x": ("sxl[s + m] = orc_mc(w[m] - wl[m], 0.5 * (wr[m] - wl[m]), wr[m] - w[m]);",
+                       "sxl[s + m] = 0.5 * (wr[m] - wl[m]);"),
 }
 
 
@@ -73,6 +83,7 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
                     "-o", str(lib), str(mut), "-lm"], check=True, cwd=tmp_path)
     env = dict(os.environ, CSH_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_kt_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
