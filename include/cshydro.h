@@ -44,6 +44,9 @@ extern "C" {
 #define CSH_F64 0
 #define CSH_F32 1
 
+#define CSH_SCHEME_MUSCL_HLL 0 /* MUSCL-Hancock, characteristic tracing, HLL (Sec. 3.3) -- default */
+#define CSH_SCHEME_KT 1        /* Kurganov-Tadmor central scheme, RK2 midpoint (Sec. 3.2)          */
+
 typedef struct csh_grid csh_grid;
 typedef struct csh_batch csh_batch;
 
@@ -72,6 +75,21 @@ int csh_init_state(csh_grid **h, int nx, int ny, double dx, double dy, int bc_x,
  * Synchronises.
  */
 int csh_set_state(csh_grid *h, const void *W, void *U);
+
+/*
+ * Select the scheme csh_step, csh_run_cfl and csh_run_dts use:
+ *   CSH_SCHEME_MUSCL_HLL (default): the characteristic MUSCL-Hancock sweep with
+ *     HLL fluxes of Sec. 3.3;
+ *   CSH_SCHEME_KT: the Kurganov-Tadmor central scheme of Sec. 3.2, eqs. (5)-(8):
+ *     local-speed flux H = (F(u-) + F(u+))/2 - a/2 (u+ - u-), a = max |u_n| +
+ *     sqrt(3 P_nn / rho) over the two face states, faces reconstructed by
+ *     component-wise MC-limited linear primitive profiles, two stages of the
+ *     Runge-Kutta midpoint rule per step, then the kick.  Two launches per step;
+ *     the first call allocates one state-sized stage buffer the handle keeps.
+ * csh_fluxes and csh_adjoint_step are those of CSH_SCHEME_MUSCL_HLL only and
+ * return CSH_ERR_ARG under CSH_SCHEME_KT.  Synchronises.
+ */
+int csh_set_scheme(csh_grid *h, int scheme);
 
 /*
  * Fixed external potential of a flat rotation curve, Phi = vc^2/2 ln(R^2 + rc^2)

@@ -25,6 +25,7 @@ BC_PERIODIC = 0
 BC_OUTFLOW = 1
 F64 = 0
 F32 = 1
+SCHEMES = {"muscl": 0, "kt": 1}
 
 
 class CshError(RuntimeError):
@@ -47,6 +48,7 @@ _SIGNATURES = [
     ("csh_init_state", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     ("csh_set_state", ctypes.c_int, [_vp, _vp, _vp]),
+    ("csh_set_scheme", ctypes.c_int, [_vp, ctypes.c_int]),
     ("csh_set_potential", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("csh_step", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp]),
     ("csh_max_signal_speed", ctypes.c_int, [_vp, _vp, _dp]),
@@ -140,6 +142,10 @@ class Grid:
         U = self.U if U is None else U
         _check(lib().csh_set_state(self._h, _dev(W, self.dtype), _dev(U, self.dtype)))
         return U
+
+    def set_scheme(self, scheme: str):
+        """"muscl" (characteristic MUSCL-Hancock + HLL, default) or "kt" (Kurganov-Tadmor)."""
+        _check(lib().csh_set_scheme(self._h, SCHEMES[scheme]))
 
     def set_potential(self, vc: float, rc: float, x0: float, y0: float = 0.0):
         _check(lib().csh_set_potential(self._h, vc, rc, x0, y0))

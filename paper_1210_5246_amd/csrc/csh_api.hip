@@ -25,6 +25,8 @@ struct csh_grid {
     int ty = 32;                    // rows per wavefront segment
     double* adj_ws = nullptr;       // adjoint workspace, allocated on first use
     size_t adj_ws_n = 0;
+    int scheme = CSH_SCHEME_MUSCL_HLL;
+    void* kt_buf = nullptr;         // stage state of the Kurganov-Tadmor scheme
     // cached graph of csh_run_cfl / csh_run_dts
     hipGraphExec_t exec = nullptr;
     int g_mode = -1, g_nsteps = -1;
@@ -75,17 +77,34 @@ hipError_t enqueue_step(csh_grid* h, const void* U, void* Un, int dev_dt, double
                         double t_end, double* dt_log, hipStream_t s, const double* dt_in = nullptr)
 {
     auto a = base_args<T>(h);
-    a.dt_in = dt_in;
     a.U = static_cast<const T*>(U);
     a.Unew = static_cast<T*>(Un);
     a.dev_dt = dev_dt;
     a.dt = dt;
+    a.dt_in = dt_in;
     a.cfl = cfl;
     a.t_end = t_end;
     a.dt_log = dt_log;
     a.s_in = h->phase;
     a.s_out = (h->phase + 1) % 3;
     a.s_reset = (h->phase + 2) % 3;
+    if (h->scheme == CSH_SCHEME_KT) {
+        // stage 1: U -> stage buffer over dt/2; records dt in slot s_in
+        auto a1 = a;
+        a1.Unew = static_cast<T*>(h->kt_buf);
+        a1.dt_log = nullptr;
+        hipError_t e = csh::launch_kt<T>(a1, h->ny > 1, false, s);
+        if (e != hipSuccess) return e;
+        // stage 2: fluxes of the stage state, update from U over dt
+        a.U = static_cast<const T*>(h->kt_buf);
+        a.Ubase = static_cast<const T*>(U);
+        if (dev_dt) {
+            a.dev_dt = 0;
+            a.dt_in = &h->slots[h->phase].dt;
+        }
+        h->phase = a.s_out;
+        return csh::launch_kt<T>(a, h->ny > 1, true, s);
+    }
     h->phase = a.s_out;
     return csh::launch_step<T>(a, h->ny > 1, false, s);
 }
@@ -196,6 +215,20 @@ extern "C" int csh_set_state(csh_grid* h, const void* W, void* U)
     return CSH_OK;
 }
 
+extern "C" int csh_set_scheme(csh_grid* h, int scheme)
+{
+    if (!h) return csh_fail(CSH_ERR_ARG, "h is NULL");
+    if (scheme != CSH_SCHEME_MUSCL_HLL && scheme != CSH_SCHEME_KT) return csh_fail(CSH_ERR_ARG, "unknown scheme");
+    if (scheme == CSH_SCHEME_KT && !h->kt_buf) {
+        const size_t bytes = 6 * (size_t)h->nx * h->ny * (h->dtype == CSH_F64 ? 8 : 4);
+        CSH_HIP(hipStreamSynchronize(h->stream));
+        CSH_HIP(hipMalloc(&h->kt_buf, bytes));
+    }
+    h->scheme = scheme;
+    drop_graph(h);
+    return CSH_OK;
+}
+
 extern "C" int csh_set_potential(csh_grid* h, double vc, double rc, double x0, double y0)
 {
     if (!h) return csh_fail(CSH_ERR_ARG, "h is NULL");
@@ -236,6 +269,7 @@ extern "C" int csh_last_signal_speed(csh_grid* h, double* s)
 extern "C" int csh_fluxes(csh_grid* h, double dt, const void* U, void* Fx, void* Fy)
 {
     if (!h || !U || !Fx || (h->ny > 1 && !Fy)) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (h->scheme != CSH_SCHEME_MUSCL_HLL) return csh_fail(CSH_ERR_ARG, "fluxes are those of the characteristic scheme");
     hipError_t e;
     if (h->dtype == CSH_F64) {
         auto a = base_args<double>(h);
@@ -348,6 +382,7 @@ extern "C" int csh_destroy(csh_grid* h)
     if (h->slots) (void)hipFree(h->slots);
     if (h->flag) (void)hipFree(h->flag);
     if (h->adj_ws) (void)hipFree(h->adj_ws);
+    if (h->kt_buf) (void)hipFree(h->kt_buf);
     delete h;
     return CSH_OK;
 }
@@ -362,6 +397,7 @@ extern "C" int csh_adjoint_step(csh_grid* h, double dt, const void* U, const voi
 {
     if (!h || !U || !lam_next || !lam) return csh_fail(CSH_ERR_ARG, "NULL argument");
     if (h->dtype != CSH_F64) return csh_fail(CSH_ERR_ARG, "the adjoint is FP64 only");
+    if (h->scheme != CSH_SCHEME_MUSCL_HLL) return csh_fail(CSH_ERR_ARG, "the adjoint is that of the characteristic scheme");
     if (lam == lam_next || lam == U) return csh_fail(CSH_ERR_ARG, "lam must not alias U or lam_next");
     if (!(dt >= 0)) return csh_fail(CSH_ERR_ARG, "dt must be >= 0");
     const size_t need = csh_adjoint_workspace_doubles(h->nx, h->ny);

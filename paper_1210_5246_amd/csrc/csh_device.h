@@ -327,6 +327,53 @@ CSH_HD Faces<T> face_states(const Prim<T>& W0, T ir, const Prim<T>& Wl, const Pr
     return f;
 }
 
+// ---- Kurganov-Tadmor central scheme (Sec. 3.2) ------------------------------------------------
+
+// component-wise MC-limited slope of the primitive variables
+template <typename T>
+CSH_HD Prim<T> mc_slope(const Prim<T>& wm, const Prim<T>& w0, const Prim<T>& wp)
+{
+    return {mc(w0.r - wm.r, wp.r - w0.r),       mc(w0.u - wm.u, wp.u - w0.u),
+            mc(w0.v - wm.v, wp.v - w0.v),       mc(w0.pxx - wm.pxx, wp.pxx - w0.pxx),
+            mc(w0.pxy - wm.pxy, wp.pxy - w0.pxy), mc(w0.pyy - wm.pyy, wp.pyy - w0.pyy)};
+}
+
+// x flux of eq. (6), H = (F(u-) + F(u+))/2 - a/2 (u+ - u-), from the face states
+// u- = wl, u+ = wr, a = max over the two of |u| + sqrt(3 Pxx / rho) (eqs. (7)-(8))
+template <typename T>
+CSH_HD Cons<T> kt_flux_x(const Prim<T>& wl, const Prim<T>& wr)
+{
+    const Cons<T> UL = to_cons(wl), UR = to_cons(wr);
+    const Cons<T> FL = flux_x(wl, UL), FR = flux_x(wr, UR);
+    const T tl = T(3) * wl.pxx, tr = T(3) * wr.pxx;
+    const T a = fmax(fabs(wl.u) + tl * rsqrt(tl * wl.r), fabs(wr.u) + tr * rsqrt(tr * wr.r));
+    const T h = T(0.5) * a;
+    return {T(0.5) * (FL.r + FR.r) - h * (UR.r - UL.r),       T(0.5) * (FL.mx + FR.mx) - h * (UR.mx - UL.mx),
+            T(0.5) * (FL.my + FR.my) - h * (UR.my - UL.my),    T(0.5) * (FL.exx + FR.exx) - h * (UR.exx - UL.exx),
+            T(0.5) * (FL.exy + FR.exy) - h * (UR.exy - UL.exy), T(0.5) * (FL.eyy + FR.eyy) - h * (UR.eyy - UL.eyy)};
+}
+
+// External flat-rotation-curve potential (Sec. 3.3, last paragraph): exact
+// kick of the velocity by dt * a for a fixed field a (rho and the stress
+// unchanged): rho u_i += dt rho a_i, E_ij += dt (a_i m_j + m_i a_j) + dt^2 rho a_i a_j.
+// P carries vc2 (0: no field), rc2, x0, y0, dx, dy of the grid.
+template <typename T, typename P>
+__device__ __forceinline__ void kick(Cons<T>& U, const P& p, double dt, int i, int j, bool twod)
+{
+    if (p.vc2 == 0.0) return;
+    const double x = p.x0 + (i + 0.5) * p.dx;
+    const double y = twod ? p.y0 + (j + 0.5) * p.dy : 0.0;
+    const double f = -p.vc2 * rcp(x * x + y * y + p.rc2);
+    const T ax = T(f * x), ay = T(f * y);
+    const T h = T(dt);
+    const T mx = U.mx, my = U.my;
+    U.mx = mx + h * U.r * ax;
+    U.my = my + h * U.r * ay;
+    U.exx = U.exx + h * ax * (T(2) * mx + h * U.r * ax);
+    U.exy = U.exy + h * (ax * my + mx * ay + h * U.r * ax * ay);
+    U.eyy = U.eyy + h * ay * (T(2) * my + h * U.r * ay);
+}
+
 // CFL rate of a cell (the timestep is C / max over cells of this):
 // (|u| + a_x)/dx + (|v| + a_y)/dy, 1-D: (|u| + a_x)/dx.
 template <typename T, bool TWOD>

@@ -34,25 +34,6 @@ __device__ __forceinline__ double step_dt(const StepArgs<T>& p, double* t_now)
     return dt;
 }
 
-// Exact kick of the velocity by dt * a for a fixed field a (rho and the stress
-// unchanged): rho u_i += dt rho a_i, E_ij += dt (a_i m_j + m_i a_j) + dt^2 rho a_i a_j.
-template <typename T>
-__device__ __forceinline__ void kick(Cons<T>& U, const StepArgs<T>& p, double dt, int i, int j, bool twod)
-{
-    if (p.vc2 == 0.0) return;
-    const double x = p.x0 + (i + 0.5) * p.dx;
-    const double y = twod ? p.y0 + (j + 0.5) * p.dy : 0.0;
-    const double f = -p.vc2 * rcp(x * x + y * y + p.rc2);
-    const T ax = T(f * x), ay = T(f * y);
-    const T h = T(dt);
-    const T mx = U.mx, my = U.my;
-    U.mx = mx + h * U.r * ax;
-    U.my = my + h * U.r * ay;
-    U.exx = U.exx + h * ax * (T(2) * mx + h * U.r * ax);
-    U.exy = U.exy + h * (ax * my + mx * ay + h * U.r * ax * ay);
-    U.eyy = U.eyy + h * ay * (T(2) * my + h * U.r * ay);
-}
-
 template <typename T>
 __device__ __forceinline__ void store_face(T* __restrict__ F, size_t plane, size_t idx, const Cons<T>& f)
 {

@@ -12,7 +12,8 @@ namespace csh {
 struct Slot {
     unsigned long long s_bits;  // max CFL rate as the bit pattern of a positive double
     double t;                   // simulation time of the state this slot describes
-    double pad[2];
+    double dt;                  // timestep a multi-stage step chose in its first stage
+    double pad;
 };
 
 constexpr int kStrip = 60;  // output columns per wavefront (64 lanes, 2 halo lanes per side)
@@ -36,6 +37,7 @@ struct StepArgs {
     const double* dt_in;     // if set (and dev_dt == 0), the timestep is read from here
     double vc2, rc2, x0, y0; // external flat-rotation-curve potential (vc2 == 0: none)
     int* flag;               // set to 1 if an output cell is not physical
+    const T* Ubase;          // two-stage schemes: state the stage update starts from (null: U)
 };
 
 template <typename T>
@@ -49,6 +51,11 @@ hipError_t launch_maxspeed(const T* U, int nx, int ny, double dx, double dy, Slo
                            hipStream_t s);
 
 hipError_t launch_reset(Slot* slots, int nslots, double t0, hipStream_t s);
+
+// Kurganov-Tadmor stage: first (half step into the stage buffer, records dt in
+// slots[s_in].dt) or final (full step from Ubase with the stage state's fluxes)
+template <typename T>
+hipError_t launch_kt(const StepArgs<T>& a, bool twod, bool final_stage, hipStream_t s);
 
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
