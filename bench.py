@@ -22,7 +22,12 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_CELL_F64 = 96     # 6 conserved planes read + 6 written, 8 B each
 BYTES_PER_CELL_F32 = 48
+# Kurganov-Tadmor step: stage 1 reads U and writes U* (96 B/cell), stage 2
+# reads U* and U and writes U^{n+1} (144 B/cell)
+BYTES_PER_CELL_KT_F64 = 240
+KT_CFL = 0.4
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -37,37 +42,50 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources (else None)."""
+def measured_counters(n):
+    """The committed rocprofv3 counter summary of the FP64 sweep (HBM bytes per
+    launch, VALU counters), if it was taken on the current kernel sources."""
     path = os.path.join(PROFILES, f"sweep_disc{n}_f64_traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     t = json.load(open(path))
     if t.get("kernel_source_hash") != sweep_source_hash():
+        return {}
+    return t
+
+
+def valu_summary(t, kernel_s, cells):
+    """FP64 VALU figures of the sweep beside its HBM roofline: the kernel sits
+    near the FP64 VALU issue limit, which is what caps its bandwidth."""
+    v = t.get("valu")
+    if not v:
         return None
-    return t.get("bytes_per_launch")
+    tflops = v["fp64_flops_per_launch"] / kernel_s / 1e12
+    return {"valu_busy": v["valu_busy"], "lane_instructions_per_cell": v["valu_lane_instructions_per_cell"],
+            "fp64_flops_per_cell": v["fp64_flops_per_cell"], "fp64_tflops": tflops,
+            "fp64_peak_tflops": FP64_PEAK_TFLOPS, "fp64_frac": tflops / FP64_PEAK_TFLOPS}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def time_graph(g, U0, steps):
+def time_graph(g, U0, steps, cfl=0.8):
     import torch
     g.U.copy_(U0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    dts = g.run_cfl(steps, 0.8)
+    dts = g.run_cfl(steps, cfl)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3, dts
 
 
 def time_kernel(g, U0, steps, dt):
-    """Average duration of the sweep kernel alone: back-to-back csh_step
-    launches on the handle's stream, bracketed by HIP events."""
+    """Average duration of one csh_step (the sweep kernel alone; both stage
+    kernels under the KT scheme): back-to-back launches on the handle's
+    stream, bracketed by HIP events."""
     import torch
     a, b = U0.clone(), torch.empty_like(U0)
     g.step(dt, a, b)
@@ -238,6 +256,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-kt", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -279,13 +298,14 @@ def main():
         dt_first = float(dts[0].item())
         log(f"{name}: {K} steps in {secs * 1e3:.2f} ms")
         kern = time_kernel(g, U0, max(K, 10), dt_first)
-        res[name] = {"secs": secs, "kernel_s": kern, "bpc": bpc}
+        res[name] = {"secs": secs, "kernel_s": kern, "bpc": bpc, "sim_t": float(dts.sum().item())}
         del g
         torch.cuda.empty_cache()
 
     f64 = res["f64"]
     value = K * cells / f64["secs"]
     achieved = f64["bpc"] * cells / f64["kernel_s"] / 1e9
+    counters = measured_counters(n)
     out = {
         "metric": "cell-updates/s (FP64 sweep, 4096^2 disc)",
         "value": value,
@@ -303,16 +323,39 @@ def main():
         "config": {"workload": f"disc {n}x{n}, FP64, {K} CFL steps at C=0.8, outflow, fixed potential",
                    "cells": cells},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counters.get("bytes_per_launch"),
                      "kernel": "sweep_kernel<double, 2-D>", "kernel_ms": f64["kernel_s"] * 1e3,
                      "kernel_source_hash": sweep_source_hash(),
-                     "algorithmic_bytes_per_launch": f64["bpc"] * cells},
+                     "algorithmic_bytes_per_launch": f64["bpc"] * cells,
+                     "valu": valu_summary(counters, f64["kernel_s"], cells)},
     }
     if "f32" in res:
         f32 = res["f32"]
         out["fp32"] = {"value": K * cells / f32["secs"], "ms_per_step": f32["secs"] / K * 1e3,
                        "kernel_ms": f32["kernel_s"] * 1e3,
                        "achieved_GBs": f32["bpc"] * cells / f32["kernel_s"] / 1e9}
+    if not args.no_kt:
+        log("kt: init + warmup")
+        g = make(torch.float64)
+        g.set_scheme("kt")
+        U0 = g.U.clone()
+        if Wm > 0:
+            g.run_cfl(Wm, KT_CFL)
+        g.U.copy_(U0)
+        g.run_cfl(K, KT_CFL)
+        torch.cuda.synchronize()
+        secs, dts = time_graph(g, U0, K, KT_CFL)
+        log(f"kt: {K} steps in {secs * 1e3:.2f} ms")
+        kern = time_kernel(g, U0, max(K, 10), float(dts[0].item()))
+        sim_t = float(dts.sum().item())
+        out["kt"] = {"value": K * cells / secs, "unit": "cell-updates/s", "ms_per_step": secs / K * 1e3,
+                     "kernel_ms_per_step": kern * 1e3, "launches_per_step": 2, "cfl": KT_CFL,
+                     "achieved_GBs": BYTES_PER_CELL_KT_F64 * cells / kern / 1e9,
+                     "step_time_vs_characteristic": secs / f64["secs"],
+                     "sim_time_per_s": sim_t / secs,
+                     "characteristic_sim_time_per_s": f64["sim_t"] / f64["secs"]}
+        del g
+        torch.cuda.empty_cache()
     if not args.no_batch:
         log("batched tubes")
         out["batched"] = bench_batched()

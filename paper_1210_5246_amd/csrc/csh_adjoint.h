@@ -116,10 +116,11 @@ CSH_HD void backproject_vjp(const P& w, const E& e, const A6& al, const P& db, P
     ab.a5 += S25b + D25b;
 }
 
-// MC: m = sgn(dc) min(2|dl|, |dc|, 2|dr|) if dl dr > 0, else 0
+// MC: m = sgn(dc) min(2|dl|, |dc|, 2|dr|) if dl and dr are nonzero with one
+// sign, else 0 (the forward form tests the signs, not the product)
 CSH_HD void mc_vjp(double dl, double dr, double mb, double& dlb, double& drb)
 {
-    if (!(dl * dr > 0.0)) return;
+    if (dl == 0.0 || dr == 0.0 || (dl < 0.0) != (dr < 0.0)) return;
     const double dc = 0.5 * (dl + dr);
     const double adc = fabs(dc), al2 = 2.0 * fabs(dl), ar2 = 2.0 * fabs(dr);
     if (adc <= al2 && adc <= ar2) {  // centred difference

@@ -202,9 +202,11 @@ CSH_HD Prim<T> backproject(const Prim<T>& w, const Eig<T>& e, const Char<T>& al)
 template <typename T>
 CSH_HD T mc(T dl, T dr)
 {
-    const T dc = T(0.5) * (dl + dr);
-    const T m = fmin(fmin(T(2) * fabs(dl), fabs(dc)), T(2) * fabs(dr));
-    return (dl * dr > T(0)) ? copysign(m, dc) : T(0);
+    // dr with dl's sign taken off is positive iff the two agree in sign; the
+    // clamp at zero then covers the extremum case
+    const T a = fmin(fabs(dl), copysign(T(1), dl) * dr);
+    const T m = fmax(fmin(a + a, T(0.5) * fabs(dl + dr)), T(0));
+    return copysign(m, dl);
 }
 
 // Limited primitive slope along x: eqs. (19)-(26) with dl = w_i - w_{i-1},
@@ -274,15 +276,15 @@ CSH_HD Cons<T> hll_x(const Face<T>& L, const Face<T>& R)
     const T sl = fmin(fmin(L.w.u - L.a, R.w.u - R.a), T(0));
     const T sr = fmax(fmax(L.w.u + L.a, R.w.u + R.a), T(0));
     const T inv = rcp(sr - sl);
-    const T slr = sl * sr;
+    const T a = sr * inv, b = sl * inv, c = sl * a;  // S_R', S_L', S_L' S_R' over S_R' - S_L'
     const Cons<T> FL = flux_x(L.w, L.U), FR = flux_x(R.w, R.U);
     Cons<T> F;
-    F.r = (sr * FL.r - sl * FR.r + slr * (R.U.r - L.U.r)) * inv;
-    F.mx = (sr * FL.mx - sl * FR.mx + slr * (R.U.mx - L.U.mx)) * inv;
-    F.my = (sr * FL.my - sl * FR.my + slr * (R.U.my - L.U.my)) * inv;
-    F.exx = (sr * FL.exx - sl * FR.exx + slr * (R.U.exx - L.U.exx)) * inv;
-    F.exy = (sr * FL.exy - sl * FR.exy + slr * (R.U.exy - L.U.exy)) * inv;
-    F.eyy = (sr * FL.eyy - sl * FR.eyy + slr * (R.U.eyy - L.U.eyy)) * inv;
+    F.r = a * FL.r - b * FR.r + c * (R.U.r - L.U.r);
+    F.mx = a * FL.mx - b * FR.mx + c * (R.U.mx - L.U.mx);
+    F.my = a * FL.my - b * FR.my + c * (R.U.my - L.U.my);
+    F.exx = a * FL.exx - b * FR.exx + c * (R.U.exx - L.U.exx);
+    F.exy = a * FL.exy - b * FR.exy + c * (R.U.exy - L.U.exy);
+    F.eyy = a * FL.eyy - b * FR.eyy + c * (R.U.eyy - L.U.eyy);
     return F;
 }
 
@@ -407,15 +409,15 @@ template <int D>
 __device__ __forceinline__ double lane_shift(double x)
 {
     constexpr int ctrl = D > 0 ? 0x130 : 0x138;
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 template <int D>
 __device__ __forceinline__ float lane_shift(float x)
 {
     constexpr int ctrl = D > 0 ? 0x130 : 0x138;
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, true));
 }
 
 template <int D, typename T>
@@ -532,6 +534,13 @@ CSH_HD int map_index(int i, int n, int bc)
         return i < 0 ? i + n : i;
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);  // zero-gradient outflow
+}
+
+// map_index for -n <= i < 2n (the stencil rows of a grid with n >= 2): no division
+CSH_HD int map_near(int i, int n, int bc)
+{
+    if (bc == 0) return i < 0 ? i + n : (i >= n ? i - n : i);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
 }  // namespace csh

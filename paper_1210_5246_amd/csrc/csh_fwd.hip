@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
         const Planes<T> in(p.U, plane);
         const OutPlanes<T> out(p.Unew, plane);
         auto load_row = [&](int r) -> Cons<T> {
-            const int gr = map_index(r, p.ny, p.bcy);
+            const int gr = map_near(r, p.ny, p.bcy);  // rows y0 - 2 .. y1 + 1, ny >= 2
             return in.load((unsigned)(gr * p.nx + gc));
         };
         // Row window in three rotating register sets: the set holding row r-1

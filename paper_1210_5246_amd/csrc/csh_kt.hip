@@ -78,23 +78,29 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
     };
 
     if constexpr (!TWOD) {
-        const Prim<T> W0 = to_prim(in.load((unsigned)gc));
+        const Cons<T> C0 = in.load((unsigned)gc);
+        const Prim<T> W0 = to_prim(C0);
         const Prim<T> s = mc_slope(lane_shift<-1>(W0), W0, lane_shift<+1>(W0));
         const Cons<T> F = kt_flux_x(half_step(W0, T(0.5), s), lane_shift<+1>(half_step(W0, T(-0.5), s)));
         const Cons<T> Fm = lane_shift<-1>(F);
-        finish(update(base.load((unsigned)gc), cx, F, Fm), c, 0);
+        finish(update(FINAL ? base.load((unsigned)gc) : C0, cx, F, Fm), c, 0);
     } else {
         const T cy = T(h / p.dy);
         const int y0 = sy * p.ty, y1 = min(y0 + p.ty, p.ny);
         auto load_row = [&](const Planes<T>& P, int r) -> Cons<T> {
-            return P.load((unsigned)(map_index(r, p.ny, p.bcy) * p.nx + gc));
+            return P.load((unsigned)(map_near(r, p.ny, p.bcy) * p.nx + gc));  // ny >= 2
         };
-        Prim<T> Wa = to_prim(load_row(in, y0 - 2)), Wb = to_prim(load_row(in, y0 - 1)), Wc = to_prim(load_row(in, y0));
+        // the first stage starts its update from its own input: the conserved
+        // rows stay in registers beside their primitive form (no second read)
+        constexpr bool kOwnBase = !FINAL;
+        Cons<T> Ca = load_row(in, y0 - 2), Cb = load_row(in, y0 - 1), Cc = load_row(in, y0);
+        Prim<T> Wa = to_prim(Ca), Wb = to_prim(Cb), Wc = to_prim(Cc);
         Prim<T> yhi_prev{};
         Cons<T> acc{};
 
-        // one row: Wm row r-1 (refilled with row r+2), W0 row r, Wp row r+1
-        auto row = [&](int r, Prim<T>& Wm, const Prim<T>& W0, const Prim<T>& Wp) {
+        // one row: Wm row r-1 (refilled with row r+2), W0 row r, Wp row r+1;
+        // Cm, C0 the conserved forms of rows r-1 and r
+        auto row = [&](int r, Prim<T>& Wm, const Prim<T>& W0, const Prim<T>& Wp, Cons<T>& Cm, const Cons<T>& C0) {
             const Cons<T> Unext = (r + 2 <= y1 + 1) ? load_row(in, r + 2) : Cons<T>{};
             const Prim<T> sxv = mc_slope(lane_shift<-1>(W0), W0, lane_shift<+1>(W0));
             const Prim<T> syv = mc_slope(Wm, W0, Wp);
@@ -110,22 +116,25 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
                     const Cons<T> F =
                         kt_flux_x(half_step(W0, T(0.5), sxv), lane_shift<+1>(half_step(W0, T(-0.5), sxv)));
                     const Cons<T> Fm = lane_shift<-1>(F);
-                    const Cons<T> B = load_row(base, r);
+                    const Cons<T> B = kOwnBase ? C0 : load_row(base, r);
                     acc = {B.r - cx * (F.r - Fm.r) + cy * G.r,           B.mx - cx * (F.mx - Fm.mx) + cy * G.mx,
                            B.my - cx * (F.my - Fm.my) + cy * G.my,       B.exx - cx * (F.exx - Fm.exx) + cy * G.exx,
                            B.exy - cx * (F.exy - Fm.exy) + cy * G.exy, B.eyy - cx * (F.eyy - Fm.eyy) + cy * G.eyy};
                 }
             }
             yhi_prev = half_step(W0, T(0.5), syv);
-            if (r + 2 <= y1 + 1) Wm = to_prim(Unext);
+            if (r + 2 <= y1 + 1) {
+                Wm = to_prim(Unext);
+                if (kOwnBase) Cm = Unext;
+            }
         };
 
         for (int r = y0 - 1; r <= y1; r += 3) {
-            row(r, Wa, Wb, Wc);
+            row(r, Wa, Wb, Wc, Ca, Cb);
             if (r + 1 > y1) break;
-            row(r + 1, Wb, Wc, Wa);
+            row(r + 1, Wb, Wc, Wa, Cb, Cc);
             if (r + 2 > y1) break;
-            row(r + 2, Wc, Wa, Wb);
+            row(r + 2, Wc, Wa, Wb, Cc, Ca);
         }
     }
 
