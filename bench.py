@@ -25,7 +25,7 @@ BYTES_PER_CELL_F32 = 48
 # Kurganov-Tadmor step: stage 1 reads U and writes U* (96 B/cell), stage 2
 # reads U* and U and writes U^{n+1} (144 B/cell)
 BYTES_PER_CELL_KT_F64 = 240
-KT_CFL = 0.4
+KT_CFL = 0.8
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 

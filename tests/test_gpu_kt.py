@@ -61,7 +61,7 @@ def test_kt_one_step_2d(shape, bc):
     g = kt_grid(w)
     og = ogrid(w)
     U0 = oracle.cons_field(w.W)
-    dt = 0.4 / oracle.max_signal_speed(og, U0)
+    dt = 0.8 / oracle.max_signal_speed(og, U0)
     ref = oracle.step_kt(og, dt, U0)
     assert max_rel_error(g.step(dt).cpu().numpy(), ref) <= TOL1
     assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
@@ -79,7 +79,7 @@ def test_kt_one_step_1d(n, bc):
     g = kt_grid(w)
     og = ogrid(w)
     U0 = oracle.cons_field(w.W)
-    dt = 0.4 / oracle.max_signal_speed(og, U0)
+    dt = 0.8 / oracle.max_signal_speed(og, U0)
     assert max_rel_error(g.step(dt).cpu().numpy(), oracle.step_kt(og, dt, U0)) <= TOL1
 
 
@@ -87,9 +87,9 @@ def test_kt_hundred_steps_periodic_512():
     """512^2 periodic, 100 device-timed CFL steps against the oracle's KT loop."""
     w = wl.periodic(512, 43, 100)
     say("kt periodic 512^2 x 100 (oracle first)")
-    ref, dts_o = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), nsteps=100, cfl=0.4, scheme="kt")
+    ref, dts_o = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), nsteps=100, cfl=0.8, scheme="kt")
     g = kt_grid(w)
-    dts = g.run_cfl(100, 0.4).cpu().numpy()
+    dts = g.run_cfl(100, 0.8).cpu().numpy()
     np.testing.assert_allclose(dts, dts_o, rtol=1e-12)
     assert max_rel_error(g.U.cpu().numpy(), ref) <= TOL100
 
@@ -102,12 +102,12 @@ def test_kt_host_dt_steps_equal_device_cfl_run_and_replay():
     dts = []
     s = g1.max_signal_speed(U)
     for _ in range(12):
-        dt = 0.4 / s
+        dt = 0.8 / s
         U = g1.step(dt, U)
         dts.append(dt)
         s = g1.last_signal_speed()
     g2 = kt_grid(w)
-    dts2 = g2.run_cfl(12, 0.4).clone()
+    dts2 = g2.run_cfl(12, 0.8).clone()
     np.testing.assert_allclose(dts2.cpu().numpy(), dts, rtol=1e-15)
     assert torch.equal(U, g2.U)
     g2.set_state(torch.from_numpy(w.W).to(DEV))
@@ -117,28 +117,27 @@ def test_kt_host_dt_steps_equal_device_cfl_run_and_replay():
 
 def test_kt_sod_tube_to_t02():
     """The Sec. 4.1 tube under KT: oracle parity, the device-clipped last step,
-    and the exact gamma = 3 solution (KT smears more than the characteristic
-    scheme: the mean density error bound is looser)."""
+    and the exact gamma = 3 solution (the bound of the oracle's own KT pin)."""
     w = wl.sod(256)
     say("kt sod 256 -> t=0.2")
-    ref, dts_o = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), cfl=0.4, t_end=0.2, scheme="kt")
+    ref, dts_o = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), cfl=0.8, t_end=0.2, scheme="kt")
     g = kt_grid(w)
-    dts = g.run_cfl(len(dts_o) + 5, 0.4, t_end=0.2).cpu().numpy()
+    dts = g.run_cfl(len(dts_o) + 5, 0.8, t_end=0.2).cpu().numpy()
     assert np.all(dts[len(dts_o):] == 0.0)
     np.testing.assert_allclose(dts[:len(dts_o)], dts_o, rtol=1e-12)
     U = g.U.cpu().numpy()
     assert max_rel_error(U, ref) <= TOL100
     assert np.all(U[2] == 0.0) and np.all(U[4] == 0.0)
     ex = er.sod_bme_solution(w.extra["x"], 0.2)
-    assert np.abs(oracle.prim_field(U)[0] - ex[0]).mean() < 1.2e-2
+    assert np.abs(oracle.prim_field(U)[0] - ex[0]).mean() < 6e-3
 
 
 def test_kt_disc_with_potential_256():
     w = wl.disc(256, 3, 10)
     say("kt disc 256^2 x 10 with potential")
-    ref, dts_o = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), nsteps=10, cfl=0.4, scheme="kt")
+    ref, dts_o = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), nsteps=10, cfl=0.8, scheme="kt")
     g = kt_grid(w)
-    dts = g.run_cfl(10, 0.4).cpu().numpy()
+    dts = g.run_cfl(10, 0.8).cpu().numpy()
     np.testing.assert_allclose(dts, dts_o, rtol=1e-12)
     assert max_rel_error(g.U.cpu().numpy(), ref) <= 1e-11
 
@@ -151,7 +150,7 @@ def test_kt_disc_4096_one_step_full():
     og = ogrid(w)
     U0 = oracle.cons_field(w.W)
     g = kt_grid(w)
-    dt = 0.4 / g.max_signal_speed()
+    dt = 0.8 / g.max_signal_speed()
     out = g.step(dt).cpu().numpy()
     assert max_rel_error(out, oracle.step_kt(og, dt, U0)) <= TOL1
 
@@ -159,9 +158,9 @@ def test_kt_disc_4096_one_step_full():
 def test_kt_fp32_close_to_fp64():
     w = wl.disc(512, 3, 5)
     say("kt fp32 disc 512^2 x 5")
-    ref, _ = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), nsteps=5, cfl=0.4, scheme="kt")
+    ref, _ = oracle.run_cfl(ogrid(w), oracle.cons_field(w.W), nsteps=5, cfl=0.8, scheme="kt")
     g = kt_grid(w, torch.float32)
-    g.run_cfl(5, 0.4)
+    g.run_cfl(5, 0.8)
     err = max_rel_error(g.U.double().cpu().numpy(), ref)
     say("kt fp32 max rel error after 5 steps:", err)
     assert err < 1e-3
@@ -172,7 +171,7 @@ def test_kt_rejects_characteristic_only_calls_and_switches_back():
     say("kt scheme switching")
     g = kt_grid(w)
     U0 = g.U.clone()
-    dt = 0.4 / g.max_signal_speed()
+    dt = 0.8 / g.max_signal_speed()
     with pytest.raises(csh.CshError):
         g.fluxes(dt)
     with pytest.raises(csh.CshError):
