@@ -114,6 +114,7 @@ def lib():
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_kt_flux.argtypes = [ctypes.c_int, _D, _D, _D]
         L.orc_step_kt.argtypes = [G, ctypes.c_double, _D, _D]
+        L.orc_fourier_amplitudes.argtypes = [G, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
         _lib = L
     return _lib
 
@@ -226,6 +227,16 @@ def step_kt(g: Grid, dt: float, U: np.ndarray) -> np.ndarray:
     U = _check(g, U); out = np.empty_like(U)
     if lib().orc_step_kt(ctypes.byref(g.c()), dt, _p(U), _p(out)) != 0:
         raise ValueError("bad grid")
+    return out
+
+
+def fourier_amplitudes(g: Grid, U: np.ndarray, m_max: int = 6, X: float = float("inf"),
+                       Y: float = float("inf")) -> np.ndarray:
+    """Global Fourier amplitudes A_1..A_m_max of the density of a 2-D state
+    (Sec. 4.4; readings F1-F3 in cshoracle.c) over the region [-X, X] x [-Y, Y]."""
+    U = _check(g, U); out = np.empty(m_max)
+    if lib().orc_fourier_amplitudes(ctypes.byref(g.c()), _p(U), int(m_max), float(X), float(Y), _p(out)) != 0:
+        raise ValueError("bad grid (2-D only) or m_max < 1")
     return out
 
 

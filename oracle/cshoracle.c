@@ -810,3 +810,57 @@ int orc_step_kt(const orc_grid *g, double dt, const double *U, double *Unew)
     free(L);
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Global Fourier amplitudes of the surface density (Sec. 4.4).            */
+/* ---------------------------------------------------------------------- */
+/*
+ * A_m = |integral over the region of Sigma exp(i m phi) dx dy| / M_d, with
+ * Sigma the density of the 2-D state.  Readings:
+ *   F1 M_d is the mass of the whole grid (sum of rho dx dy over all cells);
+ *   F2 phi is the polar angle of the cell centre in all four quadrants
+ *      (atan2(y, x)); a cell centred exactly on the origin has no angle and
+ *      is left out of the integral (it stays in M_d);
+ *   F3 the integral is the midpoint sum over the cells whose centres lie in
+ *      the closed rectangle [-X, X] x [-Y, Y] about the coordinate origin.
+ * Row sums are formed independently and added in row order, so the result
+ * does not depend on the thread count.  A[m - 1] receives A_m, m = 1..mmax.
+ */
+int orc_fourier_amplitudes(const orc_grid *g, const double *U, int mmax, double X, double Y, double *A)
+{
+    if (!grid_ok(g) || g->ny < 2 || mmax < 1) return -1;
+    const int nx = g->nx, ny = g->ny;
+    const double cell = g->dx * g->dy;
+    double *re = calloc((size_t)ny * mmax, sizeof(double));
+    double *im = calloc((size_t)ny * mmax, sizeof(double));
+    double *mass = calloc((size_t)ny, sizeof(double));
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        const double y = g->y0 + (j + 0.5) * g->dy;
+        for (int i = 0; i < nx; ++i) {
+            const double x = g->x0 + (i + 0.5) * g->dx;
+            const double sigma = U[(size_t)j * nx + i];
+            mass[j] += sigma * cell;
+            if (fabs(x) > X || fabs(y) > Y || (x == 0.0 && y == 0.0)) continue;
+            const double phi = atan2(y, x);
+            for (int m = 1; m <= mmax; ++m) {
+                re[(size_t)j * mmax + m - 1] += sigma * cos(m * phi) * cell;
+                im[(size_t)j * mmax + m - 1] += sigma * sin(m * phi) * cell;
+            }
+        }
+    }
+    double M = 0.0;
+    for (int j = 0; j < ny; ++j) M += mass[j];
+    for (int m = 1; m <= mmax; ++m) {
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < ny; ++j) {
+            sr += re[(size_t)j * mmax + m - 1];
+            si += im[(size_t)j * mmax + m - 1];
+        }
+        A[m - 1] = sqrt(sr * sr + si * si) / M;
+    }
+    free(re);
+    free(im);
+    free(mass);
+    return 0;
+}

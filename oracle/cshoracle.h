@@ -59,4 +59,7 @@ int orc_num_threads(void);
 void orc_kt_flux(int dir, const double wl[6], const double wr[6], double flux[6]);
 int orc_step_kt(const orc_grid *g, double dt, const double *U, double *Unew);
 
+/* Global Fourier amplitudes A_1..A_mmax of the density (Sec. 4.4); region [-X, X] x [-Y, Y]. */
+int orc_fourier_amplitudes(const orc_grid *g, const double *U, int mmax, double X, double Y, double *A);
+
 #endif

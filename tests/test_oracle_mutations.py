@@ -66,6 +66,14 @@ MUTANTS = {
                          "Us[m * n + c] = U[m * n + c] + dt * L[c * NV + m];"),
     "kt_unlimited_x": ("sxl[s + m] = orc_mc(w[m] - wl[m], 0.5 * (wr[m] - wl[m]), wr[m] - w[m]);",
                        "sxl[s + m] = 0.5 * (wr[m] - wl[m]);"),
+    # Fourier amplitudes: the angle as printed, arctan(y / x) (two quadrants
+    # only); the disc mass taken over the region instead of the whole grid;
+    # the mode number off by one
+    "fourier_atan_printed": ("const double phi = atan2(y, x);", "const double phi = atan(y / x);"),
+    "fourier_mass_in_region": ("            mass[j] += sigma * cell;\n            if (fabs(x) > X || fabs(y) > Y || (x == 0.0 && y == 0.0)) continue;",
+                               "            if (fabs(x) > X || fabs(y) > Y || (x == 0.0 && y == 0.0)) continue;\n            mass[j] += sigma * cell;"),
+    "fourier_mode_index": ("re[(size_t)j * mmax + m - 1] += sigma * cos(m * phi) * cell;",
+                           "re[(size_t)j * mmax + m - 1] += sigma * cos((m + 1) * phi) * cell;"),
 }
 
 
@@ -84,6 +92,7 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
     env = dict(os.environ, CSH_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_kt_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_kt_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_fourier_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
