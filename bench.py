@@ -234,6 +234,26 @@ def bench_adjoint(n=512, steps=200, K=20, ndirs=64):
             "max_fd_deviation_over_sum_abs_terms_eps1e-6": worst}
 
 
+def bench_fourier(w, reps=20):
+    """Global Fourier amplitudes A_1..A_6 of the 4096^2 disc's density: time
+    per call (two kernels plus a 48-byte copy back), HBM bandwidth at 8 B/cell."""
+    import torch
+    import paper_1210_5246_amd as csh
+    g = csh.Grid(torch.from_numpy(w.W).to("cuda"), w.dx, w.dy, (w.bcx, w.bcy))
+    A = g.fourier_amplitudes(w.x0, w.y0, 6)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.fourier_amplitudes(w.x0, w.y0, 6)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3 / reps
+    cells = w.nx * w.ny
+    return {"workload": f"A_1..A_6 of the {w.nx}x{w.ny} disc density (FP64)", "ms_per_call": secs * 1e3,
+            "cells_per_s": cells / secs, "achieved_GBs": 8 * cells / secs / 1e9, "A": A}
+
+
 def copy_probe(nbytes=1 << 30):
     """A plain device copy of known size (for calibrating the HBM byte counters)."""
     import torch
@@ -257,6 +277,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-kt", action="store_true")
+    ap.add_argument("--no-fourier", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -356,6 +377,9 @@ def main():
                      "characteristic_sim_time_per_s": f64["sim_t"] / f64["secs"]}
         del g
         torch.cuda.empty_cache()
+    if not args.no_fourier:
+        log("fourier amplitudes")
+        out["fourier"] = bench_fourier(w)
     if not args.no_batch:
         log("batched tubes")
         out["batched"] = bench_batched()

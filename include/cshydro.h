@@ -91,6 +91,28 @@ int csh_set_state(csh_grid *h, const void *W, void *U);
  */
 int csh_set_scheme(csh_grid *h, int scheme);
 
+#define CSH_FOURIER_MAX_M 16
+
+/*
+ * Global Fourier amplitudes of the surface density, the spiral-growth
+ * diagnostic of Sec. 4.4:
+ *   A_m = | sum over cells centred in [-X, X] x [-Y, Y] of rho exp(i m phi) |
+ *         / sum over all cells of rho ,   m = 1 .. m_max,
+ * with phi the polar angle (all four quadrants) of the cell centre
+ * (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy) (the same corner convention as
+ * csh_set_potential; each coordinate a product and a sum rounded separately)
+ * and rho the density plane of U.  A cell centred exactly on the origin has
+ * no angle and is left out of the numerator.
+ * U: device state [6][ny][nx] in the handle's dtype (only the density plane is
+ * read).  A: host array of m_max doubles.  1 <= m_max <= CSH_FOURIER_MAX_M,
+ * X, Y > 0 (pass HUGE_VAL for the whole grid).  2-D handles only.  The sums
+ * are formed in a fixed order (deterministic).  The first call allocates a
+ * 270 KB workspace the handle keeps.  Synchronises the handle's stream.
+ * Errors: CSH_ERR_ARG, CSH_ERR_HIP.
+ */
+int csh_fourier_amplitudes(csh_grid *h, const void *U, double x0, double y0, double X, double Y, int m_max,
+                           double *A);
+
 /*
  * Fixed external potential of a flat rotation curve, Phi = vc^2/2 ln(R^2 + rc^2)
  * centred on the coordinate origin (the analytic stand-in for the halo of

@@ -49,6 +49,8 @@ _SIGNATURES = [
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     ("csh_set_state", ctypes.c_int, [_vp, _vp, _vp]),
     ("csh_set_scheme", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("csh_fourier_amplitudes", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     ("csh_set_potential", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("csh_step", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp]),
     ("csh_max_signal_speed", ctypes.c_int, [_vp, _vp, _dp]),
@@ -146,6 +148,16 @@ class Grid:
     def set_scheme(self, scheme: str):
         """"muscl" (characteristic MUSCL-Hancock + HLL, default) or "kt" (Kurganov-Tadmor)."""
         _check(lib().csh_set_scheme(self._h, SCHEMES[scheme]))
+
+    def fourier_amplitudes(self, x0: float, y0: float, m_max: int = 6, X: float = float("inf"),
+                           Y: float = float("inf"), U: torch.Tensor | None = None) -> list[float]:
+        """Global Fourier amplitudes A_1..A_m_max of the density (``csh_fourier_amplitudes``);
+        (x0, y0) is the lower-left corner of the grid, the region [-X, X] x [-Y, Y]."""
+        U = self.U if U is None else U
+        out = (ctypes.c_double * m_max)()
+        _check(lib().csh_fourier_amplitudes(self._h, _dev(U, self.dtype), float(x0), float(y0), float(X), float(Y),
+                                            int(m_max), out))
+        return list(out)
 
     def set_potential(self, vc: float, rc: float, x0: float, y0: float = 0.0):
         _check(lib().csh_set_potential(self._h, vc, rc, x0, y0))

@@ -6,6 +6,7 @@
 #include "cshydro.h"
 #include "csh_api_util.h"
 #include "csh_internal.h"
+#include "csh_diag.h"
 
 using csh::Slot;
 
@@ -27,6 +28,7 @@ struct csh_grid {
     size_t adj_ws_n = 0;
     int scheme = CSH_SCHEME_MUSCL_HLL;
     void* kt_buf = nullptr;         // stage state of the Kurganov-Tadmor scheme
+    double* fourier_ws = nullptr;   // partial sums + amplitudes of csh_fourier_amplitudes
     // cached graph of csh_run_cfl / csh_run_dts
     hipGraphExec_t exec = nullptr;
     int g_mode = -1, g_nsteps = -1;
@@ -229,6 +231,31 @@ extern "C" int csh_set_scheme(csh_grid* h, int scheme)
     return CSH_OK;
 }
 
+extern "C" int csh_fourier_amplitudes(csh_grid* h, const void* U, double x0, double y0, double X, double Y,
+                                      int m_max, double* A)
+{
+    if (!h || !U || !A) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (h->ny < 2) return csh_fail(CSH_ERR_ARG, "Fourier amplitudes need a 2-D grid");
+    if (m_max < 1 || m_max > CSH_FOURIER_MAX_M) return csh_fail(CSH_ERR_ARG, "m_max must be in 1..CSH_FOURIER_MAX_M");
+    if (!(X > 0) || !(Y > 0)) return csh_fail(CSH_ERR_ARG, "X and Y must be > 0");
+    if (!h->fourier_ws) {
+        CSH_HIP(hipMalloc(&h->fourier_ws, sizeof(double) * ((size_t)csh::kFourierBlocks * (1 + 2 * csh::kFourierMaxM) +
+                                                            csh::kFourierMaxM)));
+    }
+    double* dA = h->fourier_ws + (size_t)csh::kFourierBlocks * (1 + 2 * csh::kFourierMaxM);
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        csh::FourierArgs<T> a{static_cast<const T*>(U), h->nx, h->ny, h->dx, h->dy, x0, y0, X, Y, m_max,
+                              h->fourier_ws, dA};
+        return csh::launch_fourier<T>(a, h->stream);
+    };
+    hipError_t e = h->dtype == CSH_F64 ? run(double{}) : run(float{});
+    if (e == hipSuccess) e = hipMemcpyAsync(A, dA, sizeof(double) * m_max, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("fourier: ") + hipGetErrorString(e));
+    return CSH_OK;
+}
+
 extern "C" int csh_set_potential(csh_grid* h, double vc, double rc, double x0, double y0)
 {
     if (!h) return csh_fail(CSH_ERR_ARG, "h is NULL");
@@ -383,6 +410,7 @@ extern "C" int csh_destroy(csh_grid* h)
     if (h->flag) (void)hipFree(h->flag);
     if (h->adj_ws) (void)hipFree(h->adj_ws);
     if (h->kt_buf) (void)hipFree(h->kt_buf);
+    if (h->fourier_ws) (void)hipFree(h->fourier_ws);
     delete h;
     return CSH_OK;
 }
