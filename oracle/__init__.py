@@ -114,6 +114,12 @@ def lib():
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_kt_flux.argtypes = [ctypes.c_int, _D, _D, _D]
         L.orc_step_kt.argtypes = [G, ctypes.c_double, _D, _D]
+        L.orc_hllc.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_hllc_star.argtypes = [ctypes.c_int, _D, _D, _D, _D, _D]
+        L.orc_step_rs.argtypes = [G, ctypes.c_int, ctypes.c_double, _D, _D]
+        L.orc_step_cells_rs.argtypes = [G, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_int64), _D]
+        L.orc_fluxes_rs.argtypes = [G, ctypes.c_int, ctypes.c_double, _D, _D, _D]
         L.orc_fourier_amplitudes.argtypes = [G, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
         _lib = L
     return _lib
@@ -180,6 +186,24 @@ def hll(direction: int, wl, wr) -> np.ndarray:
     return out
 
 
+def hllc(direction: int, wl, wr) -> np.ndarray:
+    """HLLC flux of the BME (reading H1 in cshoracle.c)."""
+    wl, wr = _vec(wl), _vec(wr); out = np.empty(6)
+    lib().orc_hllc(direction, _p(wl), _p(wr), _p(out))
+    return out
+
+
+def hllc_star(direction: int, wl, wr):
+    """(S_L, S*, S_R), U*_L, U*_R of the HLLC fan."""
+    wl, wr = _vec(wl), _vec(wr)
+    S, UsL, UsR = np.empty(3), np.empty(6), np.empty(6)
+    lib().orc_hllc_star(direction, _p(wl), _p(wr), _p(S), _p(UsL), _p(UsR))
+    return S, UsL, UsR
+
+
+SOLVERS = {"hll": 0, "hllc": 1}
+
+
 def num_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().orc_num_threads())
@@ -208,9 +232,10 @@ def _check(g: Grid, U: np.ndarray) -> np.ndarray:
     return U
 
 
-def step(g: Grid, dt: float, U: np.ndarray) -> np.ndarray:
+def step(g: Grid, dt: float, U: np.ndarray, solver: str = "hll") -> np.ndarray:
+    """One step of the characteristic scheme (Sec. 3.3) with an HLL or HLLC flux."""
     U = _check(g, U); out = np.empty_like(U)
-    if lib().orc_step(ctypes.byref(g.c()), dt, _p(U), _p(out)) != 0:
+    if lib().orc_step_rs(ctypes.byref(g.c()), SOLVERS[solver], dt, _p(U), _p(out)) != 0:
         raise ValueError("bad grid")
     return out
 
@@ -240,23 +265,23 @@ def fourier_amplitudes(g: Grid, U: np.ndarray, m_max: int = 6, X: float = float(
     return out
 
 
-def step_cells(g: Grid, dt: float, U: np.ndarray, cells) -> np.ndarray:
+def step_cells(g: Grid, dt: float, U: np.ndarray, cells, solver: str = "hll") -> np.ndarray:
     """Updated conserved state of the listed cells (flat index j*nx+i): [len(cells), 6]."""
     U = _check(g, U)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
     out = np.empty((cells.size, 6))
-    if lib().orc_step_cells(ctypes.byref(g.c()), dt, _p(U), cells.size,
-                            cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out)) != 0:
+    if lib().orc_step_cells_rs(ctypes.byref(g.c()), SOLVERS[solver], dt, _p(U), cells.size,
+                               cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out)) != 0:
         raise ValueError("bad grid")
     return out
 
 
-def fluxes(g: Grid, dt: float, U: np.ndarray):
+def fluxes(g: Grid, dt: float, U: np.ndarray, solver: str = "hll"):
     """(Fx [6, ny, nx+1], Fy [6, ny+1, nx] or None in 1-D)."""
     U = _check(g, U)
     Fx = np.empty((6, g.ny, g.nx + 1))
     Fy = np.empty((6, g.ny + 1, g.nx)) if g.ny > 1 else np.empty(6)
-    if lib().orc_fluxes(ctypes.byref(g.c()), dt, _p(U), _p(Fx), _p(Fy)) != 0:
+    if lib().orc_fluxes_rs(ctypes.byref(g.c()), SOLVERS[solver], dt, _p(U), _p(Fx), _p(Fy)) != 0:
         raise ValueError("bad grid")
     return Fx, (Fy if g.ny > 1 else None)
 
@@ -278,7 +303,8 @@ def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
     """Advance with dt = cfl / s (s from the state at the start of each step).
 
     Stops after ``nsteps`` steps, or when ``t_end`` is reached (the last step is
-    clipped to land on it).  ``scheme``: "muscl" (Sec. 3.3) or "kt" (Sec. 3.2).
+    clipped to land on it).  ``scheme``: "muscl" (Sec. 3.3, HLL flux), "hllc"
+    (Sec. 3.3 with the HLLC flux) or "kt" (Sec. 3.2).
     Returns (U, list of dt).
     """
     U = _check(g, U).copy()
@@ -295,7 +321,10 @@ def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
             raise FloatingPointError(f"timestep {dt} at step {len(dts)}: the state is not physical")
         if t_end is not None and t + dt > t_end:
             dt = t_end - t
-        U = step(g, dt, U) if scheme == "muscl" else step_kt(g, dt, U)
+        if scheme == "kt":
+            U = step_kt(g, dt, U)
+        else:
+            U = step(g, dt, U, "hllc" if scheme == "hllc" else "hll")
         dts.append(dt)
         t += dt
     return U, dts

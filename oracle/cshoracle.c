@@ -375,6 +375,103 @@ void orc_hll(int dir, const double wl[NV], const double wr[NV], double flux[NV])
     }
 }
 
+
+/* ---------------------------------------------------------------------- */
+/* HLLC Riemann flux for the BME (the solver of the paper's runs, Sec. 4.1; */
+/* its BME form is reading H1).                                             */
+/* ---------------------------------------------------------------------- */
+/*
+ * Reading H1 (the paper names HLLC but gives no BME form): Toro's three-wave
+ * solver with the outer speeds of HLL (reading R7) and one contact wave S*.
+ * The star region between S_L and S_R has one velocity (S*, v*) and one pair
+ * of normal-direction stresses (Pnn*, Pnt*) on both sides of the contact;
+ * with D_K = rho_K (S_K - u_K):
+ *   S*   = [Pnn_R - Pnn_L + D_L u_L - D_R u_R] / (D_L - D_R)
+ *   Pnn* = Pnn_K + D_K (S* - u_K)             (the same for K = L, R)
+ *   v*   = [Pnt_R - Pnt_L + D_L v_L - D_R v_R] / (D_L - D_R)
+ *   Pnt* = Pnt_K + D_K (v* - v_K)             (the same for K = L, R)
+ * (u, v the normal and transverse velocity).  Each conserved density of the
+ * star state on side K follows from the jump condition across S_K, with the
+ * star flux written as q* S* + N*, N* the non-advective part of the flux
+ * evaluated with the star quantities:
+ *   q*_K (S_K - S*) = q_K (S_K - u_K) + N* - N_K,
+ *   N = (0, Pnn, Pnt, 2 Pnn u, Pnt u + Pnn v, 2 Pnt v) for
+ *   q = (rho, rho u, rho v, Enn, Ent, Ett).
+ * The jump conditions across S_L, S* and S_R then all hold, the fan average
+ * equals the HLL state, and an isolated contact (jumps in rho and Ptt only)
+ * is kept exactly.  The flux is F_L, F*_L, F*_R or F_R by the sign pattern
+ * of S_L, S*, S_R.
+ */
+void orc_hllc_star(int dir, const double wl[NV], const double wr[NV], double speeds[3], double UsL[NV],
+                   double UsR[NV])
+{
+    const int in = (dir == 0) ? IU : IV;     /* normal velocity / momentum */
+    const int it = (dir == 0) ? IV : IU;     /* transverse */
+    const int inn = (dir == 0) ? IXX : IYY;  /* normal-normal stress / energy */
+    const int itt = (dir == 0) ? IYY : IXX;  /* transverse-transverse */
+    const double *w[2] = {wl, wr};
+    double U[2][NV];
+    orc_cons(wl, U[0]);
+    orc_cons(wr, U[1]);
+    double a[2];
+    for (int k = 0; k < 2; ++k) a[k] = sqrt(3.0 * w[k][inn] / w[k][IR]);
+    const double S[2] = {fmin(wl[in] - a[0], wr[in] - a[1]), fmax(wl[in] + a[0], wr[in] + a[1])};
+    double D[2];
+    for (int k = 0; k < 2; ++k) D[k] = w[k][IR] * (S[k] - w[k][in]);
+    const double ss = (wr[inn] - wl[inn] + D[0] * wl[in] - D[1] * wr[in]) / (D[0] - D[1]);
+    const double vs = (wr[IXY] - wl[IXY] + D[0] * wl[it] - D[1] * wr[it]) / (D[0] - D[1]);
+    const double pnn = wl[inn] + D[0] * (ss - wl[in]);
+    const double pnt = wl[IXY] + D[0] * (vs - wl[it]);
+    /* non-advective flux parts with the star quantities */
+    double Ns[NV];
+    Ns[IR] = 0.0;
+    Ns[in] = pnn;
+    Ns[it] = pnt;
+    Ns[inn] = 2.0 * pnn * ss;
+    Ns[IXY] = pnt * ss + pnn * vs;
+    Ns[itt] = 2.0 * pnt * vs;
+    for (int k = 0; k < 2; ++k) {
+        const double *wk = w[k];
+        const double u = wk[in], v = wk[it];
+        double N[NV];
+        N[IR] = 0.0;
+        N[in] = wk[inn];
+        N[it] = wk[IXY];
+        N[inn] = 2.0 * wk[inn] * u;
+        N[IXY] = wk[IXY] * u + wk[inn] * v;
+        N[itt] = 2.0 * wk[IXY] * v;
+        double *Us = k == 0 ? UsL : UsR;
+        for (int m = 0; m < NV; ++m) Us[m] = (U[k][m] * (S[k] - u) + Ns[m] - N[m]) / (S[k] - ss);
+    }
+    speeds[0] = S[0];
+    speeds[1] = ss;
+    speeds[2] = S[1];
+}
+
+void orc_hllc(int dir, const double wl[NV], const double wr[NV], double flux[NV])
+{
+    double Ul[NV], Ur[NV], Fl[NV], Fr[NV], S[3], UsL[NV], UsR[NV];
+    orc_cons(wl, Ul);
+    orc_cons(wr, Ur);
+    if (dir == 0) {
+        orc_flux_x(Ul, Fl);
+        orc_flux_x(Ur, Fr);
+    } else {
+        orc_flux_y(Ul, Fl);
+        orc_flux_y(Ur, Fr);
+    }
+    orc_hllc_star(dir, wl, wr, S, UsL, UsR);
+    if (S[0] >= 0.0) {
+        for (int m = 0; m < NV; ++m) flux[m] = Fl[m];
+    } else if (S[1] >= 0.0) {
+        for (int m = 0; m < NV; ++m) flux[m] = Fl[m] + S[0] * (UsL[m] - Ul[m]);
+    } else if (S[2] > 0.0) {
+        for (int m = 0; m < NV; ++m) flux[m] = Fr[m] + S[2] * (UsR[m] - Ur[m]);
+    } else {
+        for (int m = 0; m < NV; ++m) flux[m] = Fr[m];
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Grid driver.                                                             */
 /* ---------------------------------------------------------------------- */
@@ -422,9 +519,16 @@ static void kick(const orc_grid *g, int i, int j, double dt, double U[NV])
  * Fx / Fy (optional) receive the face fluxes: Fx[(nxi+1) * nyi], face i-1/2 of
  * interior cell i at column i; Fy[nxi * (nyi+1)].
  */
+typedef void (*riemann_fn)(int dir, const double wl[NV], const double wr[NV], double flux[NV]);
+
+static riemann_fn solver_fn(int solver)
+{
+    return solver == ORC_SOLVER_HLLC ? orc_hllc : orc_hll;
+}
+
 static void step_block(const orc_grid *g, double dt, int nxi, int nyi, int twod,
                        const double *Wp, const double *Uin, int gi0, int gj0,
-                       double *Uout, double *Fx, double *Fy)
+                       double *Uout, double *Fx, double *Fy, riemann_fn riemann)
 {
     const int px = nxi + 4;                 /* padded row length */
     const int sx = nxi + 2, sy = twod ? nyi + 2 : 1;   /* cells -1..n */
@@ -474,13 +578,13 @@ static void step_block(const orc_grid *g, double dt, int nxi, int nyi, int twod,
     #pragma omp parallel for schedule(static)
     for (int j = 0; j < nyi; ++j)
         for (int i = 0; i <= nxi; ++i) /* face i-1/2 between cells i-1 and i */
-            orc_hll(0, xhi + SIDX(i - 1, j), xlo + SIDX(i, j),
+            riemann(0, xhi + SIDX(i - 1, j), xlo + SIDX(i, j),
                     fx + ((size_t)j * (nxi + 1) + i) * NV);
     if (twod) {
         #pragma omp parallel for schedule(static)
         for (int j = 0; j <= nyi; ++j) /* face j-1/2 between cells j-1 and j */
             for (int i = 0; i < nxi; ++i)
-                orc_hll(1, yhi + SIDX(i, j - 1), ylo + SIDX(i, j),
+                riemann(1, yhi + SIDX(i, j - 1), ylo + SIDX(i, j),
                         fy + ((size_t)j * nxi + i) * NV);
     }
 
@@ -548,6 +652,11 @@ static double *padded_prim(const orc_grid *g, const double *U, int i0, int j0, i
 
 int orc_step(const orc_grid *g, double dt, const double *U, double *Unew)
 {
+    return orc_step_rs(g, ORC_SOLVER_HLL, dt, U, Unew);
+}
+
+int orc_step_rs(const orc_grid *g, int solver, double dt, const double *U, double *Unew)
+{
     if (!grid_ok(g)) return -1;
     int twod = g->ny > 1;
     size_t n = (size_t)g->nx * g->ny;
@@ -555,7 +664,7 @@ int orc_step(const orc_grid *g, double dt, const double *U, double *Unew)
     double *Uin = malloc(n * NV * sizeof(double)), *Uout = malloc(n * NV * sizeof(double));
     for (size_t c = 0; c < n; ++c)
         for (int m = 0; m < NV; ++m) Uin[c * NV + m] = U[m * n + c];
-    step_block(g, dt, g->nx, g->ny, twod, Wp, Uin, 0, 0, Uout, NULL, NULL);
+    step_block(g, dt, g->nx, g->ny, twod, Wp, Uin, 0, 0, Uout, NULL, NULL, solver_fn(solver));
     for (size_t c = 0; c < n; ++c)
         for (int m = 0; m < NV; ++m) Unew[m * n + c] = Uout[c * NV + m];
     free(Wp);
@@ -567,6 +676,12 @@ int orc_step(const orc_grid *g, double dt, const double *U, double *Unew)
 int orc_step_cells(const orc_grid *g, double dt, const double *U, int64_t ncells,
                    const int64_t *cells, double *out)
 {
+    return orc_step_cells_rs(g, ORC_SOLVER_HLL, dt, U, ncells, cells, out);
+}
+
+int orc_step_cells_rs(const orc_grid *g, int solver, double dt, const double *U, int64_t ncells,
+                      const int64_t *cells, double *out)
+{
     if (!grid_ok(g)) return -1;
     int twod = g->ny > 1;
     size_t n = (size_t)g->nx * g->ny;
@@ -577,7 +692,7 @@ int orc_step_cells(const orc_grid *g, double dt, const double *U, int64_t ncells
         double *Wp = padded_prim(g, U, i, j, 1, 1);
         double Uin[NV], Uout[NV];
         for (int m = 0; m < NV; ++m) Uin[m] = U[m * n + (size_t)c];
-        step_block(g, dt, 1, 1, twod, Wp, Uin, i, j, Uout, NULL, NULL);
+        step_block(g, dt, 1, 1, twod, Wp, Uin, i, j, Uout, NULL, NULL, solver_fn(solver));
         for (int m = 0; m < NV; ++m) out[s * NV + m] = Uout[m];
         free(Wp);
     }
@@ -585,6 +700,11 @@ int orc_step_cells(const orc_grid *g, double dt, const double *U, int64_t ncells
 }
 
 int orc_fluxes(const orc_grid *g, double dt, const double *U, double *Fx, double *Fy)
+{
+    return orc_fluxes_rs(g, ORC_SOLVER_HLL, dt, U, Fx, Fy);
+}
+
+int orc_fluxes_rs(const orc_grid *g, int solver, double dt, const double *U, double *Fx, double *Fy)
 {
     if (!grid_ok(g)) return -1;
     int twod = g->ny > 1;
@@ -597,7 +717,7 @@ int orc_fluxes(const orc_grid *g, double dt, const double *U, double *Fx, double
     size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
     double *fx = malloc(nfx * NV * sizeof(double));
     double *fy = twod ? malloc(nfy * NV * sizeof(double)) : NULL;
-    step_block(g, dt, nx, ny, twod, Wp, Uin, 0, 0, Uout, fx, fy);
+    step_block(g, dt, nx, ny, twod, Wp, Uin, 0, 0, Uout, fx, fy, solver_fn(solver));
     for (size_t f = 0; f < nfx; ++f)
         for (int m = 0; m < NV; ++m) Fx[m * nfx + f] = fx[f * NV + m];
     if (twod && Fy)

@@ -42,6 +42,17 @@ void orc_hll(int dir, const double wl[6], const double wr[6], double flux[6]);
 
 /* One step U -> Unew (may not alias), timestep dt.  Returns 0, or -1 on a bad grid. */
 int orc_step(const orc_grid *g, double dt, const double *U, double *Unew);
+
+/* Riemann solver of the characteristic scheme (the plain entry points use HLL). */
+#define ORC_SOLVER_HLL 0
+#define ORC_SOLVER_HLLC 1
+void orc_hllc(int dir, const double wl[6], const double wr[6], double flux[6]);
+void orc_hllc_star(int dir, const double wl[6], const double wr[6], double speeds[3], double UsL[6],
+                   double UsR[6]);
+int orc_step_rs(const orc_grid *g, int solver, double dt, const double *U, double *Unew);
+int orc_step_cells_rs(const orc_grid *g, int solver, double dt, const double *U, int64_t ncells,
+                      const int64_t *cells, double *out);
+int orc_fluxes_rs(const orc_grid *g, int solver, double dt, const double *U, double *Fx, double *Fy);
 /* The step for selected cells only: cells[s] = j * nx + i, out[s][6] (cell-major). */
 int orc_step_cells(const orc_grid *g, double dt, const double *U, int64_t ncells,
                    const int64_t *cells, double *out);

@@ -72,6 +72,15 @@ MUTANTS = {
     "fourier_atan_printed": ("const double phi = atan2(y, x);", "const double phi = atan(y / x);"),
     "fourier_mass_in_region": ("            mass[j] += sigma * cell;\n            if (fabs(x) > X || fabs(y) > Y || (x == 0.0 && y == 0.0)) continue;",
                                "            if (fabs(x) > X || fabs(y) > Y || (x == 0.0 && y == 0.0)) continue;\n            mass[j] += sigma * cell;"),
+    # HLLC: contact speed with the stress jump reversed; transverse star velocity
+    # without the shear-stress jump; the normal energy's stress flux halved;
+    # the star sides exchanged
+    "hllc_sstar_sign": ("const double ss = (wr[inn] - wl[inn] + D[0] * wl[in] - D[1] * wr[in]) / (D[0] - D[1]);",
+                        "const double ss = (wl[inn] - wr[inn] + D[0] * wl[in] - D[1] * wr[in]) / (D[0] - D[1]);"),
+    "hllc_vstar_no_stress": ("const double vs = (wr[IXY] - wl[IXY] + D[0] * wl[it] - D[1] * wr[it]) / (D[0] - D[1]);",
+                             "const double vs = (D[0] * wl[it] - D[1] * wr[it]) / (D[0] - D[1]);"),
+    "hllc_energy_flux": ("Ns[inn] = 2.0 * pnn * ss;", "Ns[inn] = pnn * ss;"),
+    "hllc_sides": ("} else if (S[1] >= 0.0) {", "} else if (S[1] <= 0.0) {"),
     "fourier_mode_index": ("re[(size_t)j * mmax + m - 1] += sigma * cos(m * phi) * cell;",
                            "re[(size_t)j * mmax + m - 1] += sigma * cos((m + 1) * phi) * cell;"),
 }
@@ -93,6 +102,7 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_kt_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_fourier_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_fourier_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_hllc_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
