@@ -278,6 +278,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-kt", action="store_true")
     ap.add_argument("--no-fourier", action="store_true")
+    ap.add_argument("--no-hllc", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -355,6 +356,24 @@ def main():
         out["fp32"] = {"value": K * cells / f32["secs"], "ms_per_step": f32["secs"] / K * 1e3,
                        "kernel_ms": f32["kernel_s"] * 1e3,
                        "achieved_GBs": f32["bpc"] * cells / f32["kernel_s"] / 1e9}
+    if not args.no_hllc:
+        log("hllc: init + warmup")
+        g = make(torch.float64)
+        g.set_scheme("hllc")
+        U0 = g.U.clone()
+        if Wm > 0:
+            g.run_cfl(Wm, 0.8)
+        g.U.copy_(U0)
+        g.run_cfl(K, 0.8)
+        torch.cuda.synchronize()
+        secs, dts = time_graph(g, U0, K)
+        log(f"hllc: {K} steps in {secs * 1e3:.2f} ms")
+        kern = time_kernel(g, U0, max(K, 10), float(dts[0].item()))
+        out["hllc"] = {"value": K * cells / secs, "unit": "cell-updates/s", "ms_per_step": secs / K * 1e3,
+                       "kernel_ms": kern * 1e3, "achieved_GBs": f64["bpc"] * cells / kern / 1e9,
+                       "step_time_vs_hll": secs / f64["secs"]}
+        del g
+        torch.cuda.empty_cache()
     if not args.no_kt:
         log("kt: init + warmup")
         g = make(torch.float64)

@@ -46,6 +46,7 @@ extern "C" {
 
 #define CSH_SCHEME_MUSCL_HLL 0 /* MUSCL-Hancock, characteristic tracing, HLL (Sec. 3.3) -- default */
 #define CSH_SCHEME_KT 1        /* Kurganov-Tadmor central scheme, RK2 midpoint (Sec. 3.2)          */
+#define CSH_SCHEME_MUSCL_HLLC 2 /* the characteristic sweep with the HLLC flux of the paper's runs    */
 
 typedef struct csh_grid csh_grid;
 typedef struct csh_batch csh_batch;
@@ -80,14 +81,22 @@ int csh_set_state(csh_grid *h, const void *W, void *U);
  * Select the scheme csh_step, csh_run_cfl and csh_run_dts use:
  *   CSH_SCHEME_MUSCL_HLL (default): the characteristic MUSCL-Hancock sweep with
  *     HLL fluxes of Sec. 3.3;
+ *   CSH_SCHEME_MUSCL_HLLC: the same sweep with an HLLC flux (the solver of the
+ *     paper's runs, Sec. 4.1; the paper gives no BME form): Davis outer speeds,
+ *     contact S* = (Pnn_R - Pnn_L + D_L u_L - D_R u_R) / (D_L - D_R),
+ *     D_K = rho_K (S_K - u_K), one star velocity (S*, v*) and one pair of
+ *     normal stresses (Pnn*, Pnt*) on both sides of the contact, each star
+ *     density from the jump condition across its outer wave; isolated
+ *     contacts are kept exactly;
  *   CSH_SCHEME_KT: the Kurganov-Tadmor central scheme of Sec. 3.2, eqs. (5)-(8):
  *     local-speed flux H = (F(u-) + F(u+))/2 - a/2 (u+ - u-), a = max |u_n| +
  *     sqrt(3 P_nn / rho) over the two face states, faces reconstructed by
  *     component-wise MC-limited linear primitive profiles, two stages of the
  *     Runge-Kutta midpoint rule per step, then the kick.  Two launches per step;
  *     the first call allocates one state-sized stage buffer the handle keeps.
- * csh_fluxes and csh_adjoint_step are those of CSH_SCHEME_MUSCL_HLL only and
- * return CSH_ERR_ARG under CSH_SCHEME_KT.  Synchronises.
+ * csh_fluxes returns the faces of either characteristic sweep and CSH_ERR_ARG
+ * under CSH_SCHEME_KT; csh_adjoint_step is that of CSH_SCHEME_MUSCL_HLL and
+ * returns CSH_ERR_ARG under the other schemes.  Synchronises.
  */
 int csh_set_scheme(csh_grid *h, int scheme);
 

@@ -25,7 +25,7 @@ BC_PERIODIC = 0
 BC_OUTFLOW = 1
 F64 = 0
 F32 = 1
-SCHEMES = {"muscl": 0, "kt": 1}
+SCHEMES = {"muscl": 0, "kt": 1, "hllc": 2}
 
 
 class CshError(RuntimeError):
@@ -146,7 +146,8 @@ class Grid:
         return U
 
     def set_scheme(self, scheme: str):
-        """"muscl" (characteristic MUSCL-Hancock + HLL, default) or "kt" (Kurganov-Tadmor)."""
+        """"muscl" (characteristic MUSCL-Hancock + HLL, default), "hllc" (the same sweep with
+        the HLLC flux) or "kt" (Kurganov-Tadmor)."""
         _check(lib().csh_set_scheme(self._h, SCHEMES[scheme]))
 
     def fourier_amplitudes(self, x0: float, y0: float, m_max: int = 6, X: float = float("inf"),

@@ -52,6 +52,12 @@ int rows_per_segment(int nx, int ny)
     return ty;
 }
 
+// Riemann solver of the characteristic sweep
+int solver_of(const csh_grid* h)
+{
+    return h->scheme == CSH_SCHEME_MUSCL_HLLC ? 1 : 0;
+}
+
 template <typename T>
 csh::StepArgs<T> base_args(const csh_grid* h)
 {
@@ -108,7 +114,7 @@ hipError_t enqueue_step(csh_grid* h, const void* U, void* Un, int dev_dt, double
         return csh::launch_kt<T>(a, h->ny > 1, true, s);
     }
     h->phase = a.s_out;
-    return csh::launch_step<T>(a, h->ny > 1, false, s);
+    return csh::launch_step<T>(a, h->ny > 1, false, solver_of(h), s);
 }
 
 hipError_t enqueue_maxspeed(csh_grid* h, const void* U, hipStream_t s)
@@ -220,7 +226,8 @@ extern "C" int csh_set_state(csh_grid* h, const void* W, void* U)
 extern "C" int csh_set_scheme(csh_grid* h, int scheme)
 {
     if (!h) return csh_fail(CSH_ERR_ARG, "h is NULL");
-    if (scheme != CSH_SCHEME_MUSCL_HLL && scheme != CSH_SCHEME_KT) return csh_fail(CSH_ERR_ARG, "unknown scheme");
+    if (scheme != CSH_SCHEME_MUSCL_HLL && scheme != CSH_SCHEME_KT && scheme != CSH_SCHEME_MUSCL_HLLC)
+        return csh_fail(CSH_ERR_ARG, "unknown scheme");
     if (scheme == CSH_SCHEME_KT && !h->kt_buf) {
         const size_t bytes = 6 * (size_t)h->nx * h->ny * (h->dtype == CSH_F64 ? 8 : 4);
         CSH_HIP(hipStreamSynchronize(h->stream));
@@ -296,7 +303,7 @@ extern "C" int csh_last_signal_speed(csh_grid* h, double* s)
 extern "C" int csh_fluxes(csh_grid* h, double dt, const void* U, void* Fx, void* Fy)
 {
     if (!h || !U || !Fx || (h->ny > 1 && !Fy)) return csh_fail(CSH_ERR_ARG, "NULL argument");
-    if (h->scheme != CSH_SCHEME_MUSCL_HLL) return csh_fail(CSH_ERR_ARG, "fluxes are those of the characteristic scheme");
+    if (h->scheme == CSH_SCHEME_KT) return csh_fail(CSH_ERR_ARG, "fluxes are those of the characteristic scheme");
     hipError_t e;
     if (h->dtype == CSH_F64) {
         auto a = base_args<double>(h);
@@ -305,7 +312,7 @@ extern "C" int csh_fluxes(csh_grid* h, double dt, const void* U, void* Fx, void*
         a.Fy = static_cast<double*>(Fy);
         a.dt = dt;
         a.s_in = h->phase;
-        e = csh::launch_step<double>(a, h->ny > 1, true, h->stream);
+        e = csh::launch_step<double>(a, h->ny > 1, true, solver_of(h), h->stream);
     } else {
         auto a = base_args<float>(h);
         a.U = static_cast<const float*>(U);
@@ -313,7 +320,7 @@ extern "C" int csh_fluxes(csh_grid* h, double dt, const void* U, void* Fx, void*
         a.Fy = static_cast<float*>(Fy);
         a.dt = dt;
         a.s_in = h->phase;
-        e = csh::launch_step<float>(a, h->ny > 1, true, h->stream);
+        e = csh::launch_step<float>(a, h->ny > 1, true, solver_of(h), h->stream);
     }
     if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("fluxes: ") + hipGetErrorString(e));
     return CSH_OK;
@@ -425,7 +432,8 @@ extern "C" int csh_adjoint_step(csh_grid* h, double dt, const void* U, const voi
 {
     if (!h || !U || !lam_next || !lam) return csh_fail(CSH_ERR_ARG, "NULL argument");
     if (h->dtype != CSH_F64) return csh_fail(CSH_ERR_ARG, "the adjoint is FP64 only");
-    if (h->scheme != CSH_SCHEME_MUSCL_HLL) return csh_fail(CSH_ERR_ARG, "the adjoint is that of the characteristic scheme");
+    if (h->scheme != CSH_SCHEME_MUSCL_HLL)
+        return csh_fail(CSH_ERR_ARG, "the adjoint is that of the characteristic scheme with the HLL flux");
     if (lam == lam_next || lam == U) return csh_fail(CSH_ERR_ARG, "lam must not alias U or lam_next");
     if (!(dt >= 0)) return csh_fail(CSH_ERR_ARG, "dt must be >= 0");
     const size_t need = csh_adjoint_workspace_doubles(h->nx, h->ny);

@@ -288,6 +288,52 @@ CSH_HD Cons<T> hll_x(const Face<T>& L, const Face<T>& R)
     return F;
 }
 
+// HLLC flux in x for the moment equations: outer speeds as for HLL, one
+// contact S*, and a star region with one velocity (S*, v*) and one pair of
+// x-stresses (Pxx*, Pxy*); with D_K = rho_K (S_K - u_K),
+//   S* = (Pxx_R - Pxx_L + D_L u_L - D_R u_R) / (D_L - D_R),
+//   v* = (Pxy_R - Pxy_L + D_L v_L - D_R v_R) / (D_L - D_R),
+// and each star density from the jump condition across S_K with the star
+// flux q* S* + N*:  q*_K (S_K - S*) = q_K (S_K - u_K) + N* - N_K,
+// N = (0, Pxx, Pxy, 2 Pxx u, Pxy u + Pxx v, 2 Pxy v).  The side K of the
+// contact that holds x = 0 is selected first (S* >= 0: left), so one star
+// state is formed; with S_K' the outer speed clamped at 0 the flux is
+// F_K + S_K' (U*_K - U_K), which is F_L / F_R in the supersonic cases.
+template <typename T>
+CSH_HD Cons<T> hllc_x(const Face<T>& L, const Face<T>& R)
+{
+    const T sl = fmin(L.w.u - L.a, R.w.u - R.a);
+    const T sr = fmax(L.w.u + L.a, R.w.u + R.a);
+    const T dl = L.w.r * (sl - L.w.u), dr = R.w.r * (sr - R.w.u);
+    const T idd = rcp(dl - dr);
+    const T ss = (R.w.pxx - L.w.pxx + dl * L.w.u - dr * R.w.u) * idd;
+    const T vs = (R.w.pxy - L.w.pxy + dl * L.w.v - dr * R.w.v) * idd;
+    const bool left = ss >= T(0);
+    const Face<T>& K = left ? L : R;
+    const T sk = left ? sl : sr, dk = left ? dl : dr;
+    const T skc = left ? fmin(sl, T(0)) : fmax(sr, T(0));
+    const Prim<T>& w = K.w;
+    const T pnn = w.pxx + dk * (ss - w.u), pnt = w.pxy + dk * (vs - w.v);
+    const T g = skc * rcp(sk - ss);  // S_K' / (S_K - S*)
+    // S_K' (U*_K - U_K) = S_K' [U_K (S* - u_K) + N* - N_K] / (S_K - S*)
+    const T c = ss - w.u;
+    const Cons<T> F = flux_x(w, K.U);
+    return {F.r + g * (K.U.r * c),
+            F.mx + g * (K.U.mx * c + pnn - w.pxx),
+            F.my + g * (K.U.my * c + pnt - w.pxy),
+            F.exx + g * (K.U.exx * c + T(2) * (pnn * ss - w.pxx * w.u)),
+            F.exy + g * (K.U.exy * c + pnt * ss + pnn * vs - w.pxy * w.u - w.pxx * w.v),
+            F.eyy + g * (K.U.eyy * c + T(2) * (pnt * vs - w.pxy * w.v))};
+}
+
+// The face flux of the characteristic scheme: RS = 0 HLL, RS = 1 HLLC.
+template <int RS, typename T>
+CSH_HD Cons<T> riemann_x(const Face<T>& L, const Face<T>& R)
+{
+    if constexpr (RS == 1) return hllc_x(L, R);
+    else return hll_x(L, R);
+}
+
 template <typename T>
 CSH_HD Face<T> swap(const Face<T>& f)
 {
@@ -453,13 +499,13 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double 
 // conserved states of the 64 consecutive cells the wavefront holds: slopes,
 // characteristic limiting, tracing (eqs. (19)-(32)), HLL.  Valid on lanes
 // 1..61 (the two edge lanes on each side lack a neighbour's slope).
-template <typename T>
+template <typename T, int RS = 0>
 __device__ __forceinline__ Cons<T> flux_1d(const Cons<T>& U0, T kx)
 {
     const T ir = rcp(U0.r);
     const Prim<T> W0 = to_prim(U0, ir);
     const Faces<T> f = face_states<T, false>(W0, ir, lane_shift<-1>(W0), lane_shift<+1>(W0), W0, W0, kx, T(0));
-    return hll_x(make_face_x(f.xhi), make_face_x(lane_shift<+1>(f.xlo)));
+    return riemann_x<RS>(make_face_x(f.xhi), make_face_x(lane_shift<+1>(f.xlo)));
 }
 
 template <typename T>

@@ -40,7 +40,7 @@ __device__ __forceinline__ void store_face(T* __restrict__ F, size_t plane, size
     store_cons(F, plane, idx, f);
 }
 
-template <typename T, bool TWOD, bool FLUXES>
+template <typename T, bool TWOD, bool FLUXES, int RS>
 __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
 {
     double t_now;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
 
     if constexpr (!TWOD) {
         const Cons<T> U0 = load_cons(p.U, plane, (size_t)gc);
-        const Cons<T> F = flux_1d(U0, kx);  // face c + 1/2
+        const Cons<T> F = flux_1d<T, RS>(U0, kx);  // face c + 1/2
         if constexpr (FLUXES) {
             // lanes 1..61 hold faces x0 - 1/2 .. x0 + 59 + 1/2
             if (lane >= 1 && lane <= 1 + kStrip && c >= -1 && c <= p.nx - 1)
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
 
             if (r >= y0) {
                 // y face r - 1/2 between the cell below (its high state) and this cell (low state)
-                const Cons<T> G = swap(hll_x(make_face_x(swap(yhi_prev)), make_face_x(swap(fs.ylo))));
+                const Cons<T> G = swap(riemann_x<RS>(make_face_x(swap(yhi_prev)), make_face_x(swap(fs.ylo))));
                 if constexpr (FLUXES) {
                     if (own) store_face(p.Fy, (size_t)p.nx * (p.ny + 1), (size_t)r * p.nx + c, G);
                 } else if (r > y0) {  // finish cell (c, r - 1)
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
                 }
                 if (r < y1) {
                     // x faces of row r, then start the update of (c, r) with its low y face
-                    const Cons<T> F = hll_x(make_face_x(fs.xhi), make_face_x(lane_shift<+1>(fs.xlo)));
+                    const Cons<T> F = riemann_x<RS>(make_face_x(fs.xhi), make_face_x(lane_shift<+1>(fs.xlo)));
                     if constexpr (FLUXES) {
                         if (lane >= 1 && lane <= 1 + kStrip && c >= -1 && c <= p.nx - 1)
                             store_face(p.Fx, (size_t)(p.nx + 1) * p.ny, (size_t)r * (p.nx + 1) + (c + 1), F);
@@ -163,18 +163,25 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
     if (__any(bad) && lane == 0) atomicOr(p.flag, 1);
 }
 
+template <typename T, int RS>
+void launch_sweep(const StepArgs<T>& a, bool twod, bool fluxes, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (twod) {
+        if (fluxes) sweep_kernel<T, true, true, RS><<<grid, block, 0, s>>>(a);
+        else sweep_kernel<T, true, false, RS><<<grid, block, 0, s>>>(a);
+    } else {
+        if (fluxes) sweep_kernel<T, false, true, RS><<<grid, block, 0, s>>>(a);
+        else sweep_kernel<T, false, false, RS><<<grid, block, 0, s>>>(a);
+    }
+}
+
 template <typename T>
-hipError_t launch_step(const StepArgs<T>& a, bool twod, bool fluxes, hipStream_t s)
+hipError_t launch_step(const StepArgs<T>& a, bool twod, bool fluxes, int solver, hipStream_t s)
 {
     const int nwaves = a.nstrips * a.nsegs;
     const dim3 grid((nwaves + kWaves - 1) / kWaves), block(64 * kWaves);
-    if (twod) {
-        if (fluxes) sweep_kernel<T, true, true><<<grid, block, 0, s>>>(a);
-        else sweep_kernel<T, true, false><<<grid, block, 0, s>>>(a);
-    } else {
-        if (fluxes) sweep_kernel<T, false, true><<<grid, block, 0, s>>>(a);
-        else sweep_kernel<T, false, false><<<grid, block, 0, s>>>(a);
-    }
+    if (solver == 1) launch_sweep<T, 1>(a, twod, fluxes, grid, block, s);
+    else launch_sweep<T, 0>(a, twod, fluxes, grid, block, s);
     return hipGetLastError();
 }
 
@@ -265,7 +272,7 @@ hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t s)
 }
 
 #define CSH_INSTANTIATE(T)                                                                         \
-    template hipError_t launch_step<T>(const StepArgs<T>&, bool, bool, hipStream_t);               \
+    template hipError_t launch_step<T>(const StepArgs<T>&, bool, bool, int, hipStream_t);               \
     template hipError_t launch_init<T>(const T*, T*, int64_t, int*, hipStream_t);                  \
     template hipError_t launch_maxspeed<T>(const T*, int, int, double, double, Slot*, int*,        \
                                            hipStream_t);                                           \

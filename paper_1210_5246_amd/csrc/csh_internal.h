@@ -40,8 +40,9 @@ struct StepArgs {
     const T* Ubase;          // two-stage schemes: state the stage update starts from (null: U)
 };
 
+// solver: 0 HLL, 1 HLLC
 template <typename T>
-hipError_t launch_step(const StepArgs<T>& a, bool twod, bool fluxes, hipStream_t s);
+hipError_t launch_step(const StepArgs<T>& a, bool twod, bool fluxes, int solver, hipStream_t s);
 
 template <typename T>
 hipError_t launch_init(const T* W, T* U, int64_t n, int* flag, hipStream_t s);
