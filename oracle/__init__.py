@@ -31,6 +31,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cshoracle.c")
+_SRC3 = os.path.join(_HERE, "cshoracle3.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 # A test may point the shim at a differently built copy (planted-mistake checks).
 _LIB_OVERRIDE = os.environ.get("CSH_ORACLE_LIB")
@@ -41,10 +42,11 @@ BC_OUTFLOW = 1
 
 def build(force: bool = True) -> str:
     """Compile the oracle with the host C compiler (gcc)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(f) for f in (_SRC, _SRC3))
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
         tmp = _LIB_PATH + f".tmp{os.getpid()}"
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
-               "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-std=c99", "-Wall", "-o", tmp, _SRC, _SRC3, "-lm"]
         subprocess.run(cmd, check=True, cwd=_HERE)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -77,6 +79,27 @@ class Grid:
                      self.x0, self.y0, self.vc, self.rc)
 
 
+class _Grid3(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("h", ctypes.c_double * 3), ("bc", ctypes.c_int * 3)]
+
+
+@dataclass
+class Grid3:
+    """Uniform 3-D grid: cells (nx, ny, nz), sizes (dx, dy, dz), boundary kinds per axis."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    bc: tuple = (BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
+
+    def c(self) -> _Grid3:
+        return _Grid3((ctypes.c_int * 3)(self.nx, self.ny, self.nz),
+                      (ctypes.c_double * 3)(self.dx, self.dy, self.dz),
+                      (ctypes.c_int * 3)(*self.bc))
+
+
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
 
@@ -87,7 +110,8 @@ def lib():
         if _LIB_OVERRIDE:
             L = ctypes.CDLL(_LIB_OVERRIDE)
         else:
-            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+                    os.path.getmtime(_SRC), os.path.getmtime(_SRC3)):
                 build(force=True)
             L = ctypes.CDLL(_LIB_PATH)
         G = ctypes.POINTER(_Grid)
@@ -120,6 +144,19 @@ def lib():
         L.orc_step_cells_rs.argtypes = [G, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int64,
                                         ctypes.POINTER(ctypes.c_int64), _D]
         L.orc_fluxes_rs.argtypes = [G, ctypes.c_int, ctypes.c_double, _D, _D, _D]
+        G3 = ctypes.POINTER(_Grid3)
+        for name in ("orc3_cons", "orc3_prim"):
+            getattr(L, name).argtypes = [_D, _D]
+        L.orc3_flux.argtypes = [ctypes.c_int, _D, _D]
+        L.orc3_jac.argtypes = [ctypes.c_int, _D, _D]
+        L.orc3_eigen.argtypes = [ctypes.c_int, _D, _D, _D, _D]
+        L.orc3_limited_slope.argtypes = [ctypes.c_int, _D, _D, _D, _D]
+        L.orc3_trace.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, _D, _D]
+        L.orc3_hll.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc3_step.argtypes = [G3, ctypes.c_double, _D, _D]
+        L.orc3_step_cells.argtypes = [G3, ctypes.c_double, _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _D]
+        L.orc3_max_signal_speed.argtypes = [G3, _D]
+        L.orc3_max_signal_speed.restype = ctypes.c_double
         L.orc_fourier_amplitudes.argtypes = [G, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D]
         _lib = L
     return _lib
@@ -253,6 +290,118 @@ def step_kt(g: Grid, dt: float, U: np.ndarray) -> np.ndarray:
     if lib().orc_step_kt(ctypes.byref(g.c()), dt, _p(U), _p(out)) != 0:
         raise ValueError("bad grid")
     return out
+
+
+# ---- three dimensions (cshoracle3.c) ---------------------------------------------------
+
+def cons3(w) -> np.ndarray:
+    w = _vec(w); out = np.empty(10); lib().orc3_cons(_p(w), _p(out)); return out
+
+
+def prim3(U) -> np.ndarray:
+    U = _vec(U); out = np.empty(10); lib().orc3_prim(_p(U), _p(out)); return out
+
+
+def flux3(axis: int, U) -> np.ndarray:
+    U = _vec(U); out = np.empty(10); lib().orc3_flux(axis, _p(U), _p(out)); return out
+
+
+def jac3(axis: int, w) -> np.ndarray:
+    w = _vec(w); A = np.empty((10, 10)); lib().orc3_jac(axis, _p(w), _p(A)); return A
+
+
+def eigen3(axis: int, w):
+    """(lambda [10], R [10,10] right eigenvectors as columns, L = R^-1)."""
+    w = _vec(w); lam, R, L = np.empty(10), np.empty((10, 10)), np.empty((10, 10))
+    if lib().orc3_eigen(axis, _p(w), _p(lam), _p(R), _p(L)) != 1:
+        raise ValueError("singular eigenvector matrix")
+    return lam, R, L
+
+
+def limited_slope3(axis: int, wm, w0, wp) -> np.ndarray:
+    out = np.empty(10)
+    lib().orc3_limited_slope(axis, _p(_vec(wm)), _p(_vec(w0)), _p(_vec(wp)), _p(out))
+    return out
+
+
+def trace3(axis: int, w, dw, k: float):
+    lo, hi = np.empty(10), np.empty(10)
+    lib().orc3_trace(axis, _p(_vec(w)), _p(_vec(dw)), float(k), _p(lo), _p(hi))
+    return lo, hi
+
+
+def hll3(axis: int, wl, wr) -> np.ndarray:
+    out = np.empty(10); lib().orc3_hll(axis, _p(_vec(wl)), _p(_vec(wr)), _p(out)); return out
+
+
+def _check3(g: Grid3, U: np.ndarray) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    if U.size != 10 * g.nx * g.ny * g.nz:
+        raise ValueError("state has the wrong size for the grid")
+    return U
+
+
+_PIDX3 = ((4, 5, 6), (5, 7, 8), (6, 8, 9))
+
+
+def cons3_field(W: np.ndarray) -> np.ndarray:
+    """Primitive [10, ...] -> conserved [10, ...]: E_ij = P_ij + rho u_i u_j (Sec. 2)."""
+    W = np.asarray(W, dtype=np.float64)
+    U = np.empty_like(W)
+    U[0] = W[0]
+    for i in range(3):
+        U[1 + i] = W[0] * W[1 + i]
+        for j in range(i, 3):
+            U[_PIDX3[i][j]] = W[_PIDX3[i][j]] + W[0] * W[1 + i] * W[1 + j]
+    return U
+
+
+def prim3_field(U: np.ndarray) -> np.ndarray:
+    U = np.asarray(U, dtype=np.float64)
+    W = np.empty_like(U)
+    W[0] = U[0]
+    for i in range(3):
+        W[1 + i] = U[1 + i] / U[0]
+    for i in range(3):
+        for j in range(i, 3):
+            W[_PIDX3[i][j]] = U[_PIDX3[i][j]] - U[0] * W[1 + i] * W[1 + j]
+    return W
+
+
+def step3(g: Grid3, dt: float, U: np.ndarray) -> np.ndarray:
+    """One step of the 3-D characteristic scheme with HLL fluxes; U [10, nz, ny, nx]."""
+    U = _check3(g, U); out = np.empty_like(U)
+    if lib().orc3_step(ctypes.byref(g.c()), dt, _p(U), _p(out)) != 0:
+        raise ValueError("bad grid")
+    return out
+
+
+def step3_cells(g: Grid3, dt: float, U: np.ndarray, cells) -> np.ndarray:
+    """Updated states of the listed cells (flat index (k ny + j) nx + i): [len(cells), 10]."""
+    U = _check3(g, U)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.empty((cells.size, 10))
+    if lib().orc3_step_cells(ctypes.byref(g.c()), dt, _p(U), cells.size,
+                             cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(out)) != 0:
+        raise ValueError("bad grid")
+    return out
+
+
+def max_signal_speed3(g: Grid3, U: np.ndarray) -> float:
+    return lib().orc3_max_signal_speed(ctypes.byref(g.c()), _p(_check3(g, U)))
+
+
+def run_cfl3(g: Grid3, U: np.ndarray, nsteps: int, cfl: float = 0.8):
+    """nsteps 3-D steps with dt = cfl / s from the state at the start of each step."""
+    U = _check3(g, U).copy()
+    dts = []
+    for _ in range(nsteps):
+        dt = cfl / max_signal_speed3(g, U)
+        if not (dt > 0.0 and dt < float("inf")):
+            raise FloatingPointError(f"timestep {dt}: the state is not physical")
+        U = step3(g, dt, U)
+        dts.append(dt)
+    return U, dts
 
 
 def fourier_amplitudes(g: Grid, U: np.ndarray, m_max: int = 6, X: float = float("inf"),

@@ -73,4 +73,24 @@ int orc_step_kt(const orc_grid *g, double dt, const double *U, double *Unew);
 /* Global Fourier amplitudes A_1..A_mmax of the density (Sec. 4.4); region [-X, X] x [-Y, Y]. */
 int orc_fourier_amplitudes(const orc_grid *g, const double *U, int mmax, double X, double Y, double *A);
 
+/* ---- three dimensions (cshoracle3.c): ten-moment system, HLL ---- */
+typedef struct {
+    int n[3];      /* cells along x, y, z */
+    double h[3];   /* cell sizes */
+    int bc[3];     /* ORC_BC_PERIODIC / ORC_BC_OUTFLOW per axis */
+} orc_grid3;
+
+void orc3_cons(const double w[10], double U[10]);
+void orc3_prim(const double U[10], double w[10]);
+void orc3_flux(int k, const double U[10], double F[10]);
+void orc3_jac(int k, const double w[10], double A[10][10]);
+int orc3_eigen(int n, const double w[10], double lam[10], double R[10][10], double L[10][10]);
+void orc3_limited_slope(int n, const double wm[10], const double w0[10], const double wp[10], double dwm[10]);
+void orc3_trace(int n, const double w[10], const double dwm[10], double k, double w_lo[10], double w_hi[10]);
+void orc3_hll(int n, const double wl[10], const double wr[10], double flux[10]);
+int orc3_step(const orc_grid3 *g, double dt, const double *U, double *Unew);
+int orc3_step_cells(const orc_grid3 *g, double dt, const double *U, int64_t ncells, const int64_t *cells,
+                    double *out);
+double orc3_max_signal_speed(const orc_grid3 *g, const double *U);
+
 #endif

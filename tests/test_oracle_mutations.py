@@ -15,6 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "cshoracle.c")
+SRC3 = os.path.join(ROOT, "oracle", "cshoracle3.c")
 
 MUTANTS = {
     # eq. (28) as printed: 1/2 - max(lam0, 0) k instead of 1/2 + min(lam0, 0) k
@@ -81,6 +82,15 @@ MUTANTS = {
                              "const double vs = (D[0] * wl[it] - D[1] * wr[it]) / (D[0] - D[1]);"),
     "hllc_energy_flux": ("Ns[inn] = 2.0 * pnn * ss;", "Ns[inn] = pnn * ss;"),
     "hllc_sides": ("} else if (S[1] >= 0.0) {", "} else if (S[1] <= 0.0) {"),
+    # three dimensions: a flux term dropped, a Jacobian entry on the wrong
+    # velocity, a shear eigenvector sign, half the transverse predictor on the
+    # high faces, the CFL sum without z
+    "flux3_term": ("F[pidx(i, j)] = U[pidx(i, j)] * uk + w[pidx(k, i)] * w[1 + j] + w[pidx(k, j)] * w[1 + i];",
+                   "F[pidx(i, j)] = U[pidx(i, j)] * uk + w[pidx(k, i)] * w[1 + j];"),
+    "jac3_entry": ("A[r][1 + i] += w[pidx(j, k)];", "A[r][1 + i] += w[pidx(i, k)];"),
+    "eigen3_shear_sign": ("R[pidx(n, ts)][cidx] = pnn;", "R[pidx(n, ts)][cidx] = -pnn;"),
+    "transverse3_half": ("hi[m] -= kf[o2] * Adw[o2][m];", "hi[m] -= 0.5 * kf[o2] * Adw[o2][m];"),
+    "cfl3_no_z": ("for (int k = 0; k < 3; ++k) s += (fabs(w[1 + k])", "for (int k = 0; k < 2; ++k) s += (fabs(w[1 + k])"),
     "fourier_mode_index": ("re[(size_t)j * mmax + m - 1] += sigma * cos(m * phi) * cell;",
                            "re[(size_t)j * mmax + m - 1] += sigma * cos((m + 1) * phi) * cell;"),
 }
@@ -89,20 +99,24 @@ MUTANTS = {
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_fails_a_pin(name, tmp_path):
     old, new = MUTANTS[name]
-    src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation site not found uniquely: {name}"
-    mut = tmp_path / "cshoracle.c"
-    mut.write_text(src.replace(old, new))
+    srcs = {p: open(p).read() for p in (SRC, SRC3)}
+    hits = [p for p, t in srcs.items() if t.count(old) == 1]
+    assert len(hits) == 1 and sum(t.count(old) for t in srcs.values()) == 1, \
+        f"mutation site not found uniquely: {name}"
+    for p, t in srcs.items():
+        (tmp_path / os.path.basename(p)).write_text(t.replace(old, new) if p == hits[0] else t)
     for h in ("cshoracle.h",):
         (tmp_path / h).write_text(open(os.path.join(ROOT, "oracle", h)).read())
     lib = tmp_path / "libmut.so"
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                    "-o", str(lib), str(mut), "-lm"], check=True, cwd=tmp_path)
+                    "-o", str(lib), str(tmp_path / "cshoracle.c"), str(tmp_path / "cshoracle3.c"), "-lm"],
+                   check=True, cwd=tmp_path)
     env = dict(os.environ, CSH_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_kt_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_fourier_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_hllc_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_hllc_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle3_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"

@@ -220,3 +220,57 @@ def fd_directions(n: int, count: int = 64, base_seed: int = 1000) -> list:
         d /= np.abs(d).max(axis=(1, 2), keepdims=True)
         dirs.append(d)
     return dirs
+
+
+# ---- three dimensions ---------------------------------------------------------------------------
+
+def smooth_gaussian3(g: np.random.Generator, shape, width: float = 4.0) -> np.ndarray:
+    """3-D periodic Gaussian-smoothed white noise, zero mean, unit std."""
+    white = g.standard_normal(shape)
+    k0 = np.fft.fftfreq(shape[0])[:, None, None]
+    k1 = np.fft.fftfreq(shape[1])[None, :, None]
+    k2 = np.fft.rfftfreq(shape[2])[None, None, :]
+    kernel_hat = np.exp(-2.0 * (math.pi * width) ** 2 * (k0 * k0 + k1 * k1 + k2 * k2))
+    f = np.fft.irfftn(np.fft.rfftn(white) * kernel_hat, s=shape, axes=(0, 1, 2))
+    f -= f.mean()
+    f /= f.std()
+    return f
+
+
+@dataclass
+class Workload3:
+    name: str
+    W: np.ndarray            # primitive fields [10, nz, ny, nx]:
+                             # rho, u, v, w, Pxx, Pxy, Pxz, Pyy, Pyz, Pzz
+    n: tuple                 # (nx, ny, nz)
+    h: tuple                 # (dx, dy, dz)
+    bc: tuple                # boundary kind per axis
+    nsteps: int | None = None
+
+
+def periodic3(nx: int = 64, ny: int | None = None, nz: int | None = None, seed: int = 7,
+              nsteps: int = 20, width: float = 4.0) -> Workload3:
+    """3-D periodic random state on [0,1]^3, the 2-D periodic recipe in three
+    dimensions: rho = exp(0.3 g1), velocities 0.1 g2..g4, P = rho L L^T with
+    L lower triangular, diagonal 0.5 + 0.5 Phi(g), off-diagonal -0.2 + 0.4 Phi(g)
+    (g: smooth fields of width ``width`` cells)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    r = rng(seed)
+    shape = (nz, ny, nx)
+    gs = [smooth_gaussian3(r, shape, width) for _ in range(10)]
+    W = np.empty((10,) + shape)
+    W[0] = np.exp(0.3 * gs[0])
+    W[1:4] = 0.1 * np.stack(gs[1:4])
+    L = np.zeros((3, 3) + shape)
+    L[0, 0] = 0.5 + 0.5 * ndtr(gs[4])
+    L[1, 1] = 0.5 + 0.5 * ndtr(gs[5])
+    L[2, 2] = 0.5 + 0.5 * ndtr(gs[6])
+    L[1, 0] = -0.2 + 0.4 * ndtr(gs[7])
+    L[2, 0] = -0.2 + 0.4 * ndtr(gs[8])
+    L[2, 1] = -0.2 + 0.4 * ndtr(gs[9])
+    P = np.einsum("ik...,jk...->ij...", L, L)
+    for (i, j), m in zip(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)), range(4, 10)):
+        W[m] = W[0] * P[i, j]
+    return Workload3("periodic3d", W, (nx, ny, nz), (1.0 / nx, 1.0 / ny, 1.0 / nz),
+                     (BC_PERIODIC,) * 3, nsteps)
