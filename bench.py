@@ -26,6 +26,11 @@ BYTES_PER_CELL_F32 = 48
 # reads U* and U and writes U^{n+1} (144 B/cell)
 BYTES_PER_CELL_KT_F64 = 240
 KT_CFL = 0.8
+# 3-D: 10 planes read + 10 written = 160 B per cell-update for a single pass;
+# the two-kernel design also writes six face states (480 B) and reads them
+# twice (960 B): 1600 B
+BYTES_PER_CELL_3D_MIN = 160
+BYTES_PER_CELL_3D_DESIGN = 1600
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 
@@ -254,6 +259,33 @@ def bench_fourier(w, reps=20):
             "cells_per_s": cells / secs, "achieved_GBs": 8 * cells / secs / 1e9, "A": A}
 
 
+def bench_3d(n=256, steps=10):
+    """The 3-D ten-moment sweep on a periodic n^3 random state (FP64): graph-
+    replayed device-timed steps; bandwidth at the design's bytes per cell."""
+    import torch
+    import workloads as wl
+    import paper_1210_5246_amd as csh
+    w = wl.periodic3(n, seed=7)
+    G = csh.Grid3(torch.from_numpy(w.W).to("cuda"), w.h, w.bc)
+    del w
+    U0 = G.U.clone()
+    G.run_cfl(steps, 0.8)                   # records the graph
+    G.U.copy_(U0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    G.run_cfl(steps, 0.8)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    cells = n ** 3
+    return {"workload": f"periodic {n}^3 ten-moment state, FP64, {steps} CFL steps at C=0.8, HLL",
+            "value": steps * cells / secs, "unit": "cell-updates/s", "ms_per_step": secs / steps * 1e3,
+            "algorithmic_bytes_per_cell": BYTES_PER_CELL_3D_MIN,
+            "design_bytes_per_cell": BYTES_PER_CELL_3D_DESIGN,
+            "achieved_GBs_design": BYTES_PER_CELL_3D_DESIGN * cells * steps / secs / 1e9}
+
+
 def copy_probe(nbytes=1 << 30):
     """A plain device copy of known size (for calibrating the HBM byte counters)."""
     import torch
@@ -279,6 +311,7 @@ def main():
     ap.add_argument("--no-kt", action="store_true")
     ap.add_argument("--no-fourier", action="store_true")
     ap.add_argument("--no-hllc", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -399,6 +432,10 @@ def main():
     if not args.no_fourier:
         log("fourier amplitudes")
         out["fourier"] = bench_fourier(w)
+    if not args.no_3d:
+        log("3-D sweep")
+        out["sweep3d"] = bench_3d()
+        torch.cuda.empty_cache()
     if not args.no_batch:
         log("batched tubes")
         out["batched"] = bench_batched()

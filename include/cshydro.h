@@ -246,6 +246,51 @@ int csh_batch_autotune(csh_batch *b, int probe_steps, double cfl, const void *U,
 
 int csh_batch_destroy(csh_batch *b);
 
+/* ======================================================================
+ * Three dimensions: the ten-moment system (Sec. 2, eqs. (2)-(4) in three
+ * dimensions; ten eigenvalues, Sec. 3.3), FP64, HLL, no external potential.
+ * U = (rho, rho u, rho v, rho w, Exx, Exy, Exz, Eyy, Eyz, Ezz) and
+ * W = (rho, u, v, w, Pxx, Pxy, Pxz, Pyy, Pyz, Pzz), device arrays
+ * [10][nz][ny][nx] (x fastest).  The scheme is the characteristic sweep of
+ * Sec. 3.3 along all three axes: MC slopes of the ten wave amplitudes, the
+ * Hancock predictor with the transverse terms of both other axes, HLL fluxes
+ * with Davis speeds, the unsplit update; timestep C / max over cells of
+ * sum_k (|u_k| + sqrt(3 P_kk / rho)) / h_k.
+ * ====================================================================== */
+typedef struct csh3_grid csh3_grid;
+
+/* Message of the last failed csh3_* call on this thread. */
+const char *csh3_last_error(void);
+
+/*
+ * Create a 3-D handle and convert W to U (validation as csh_init_state:
+ * rho > 0 and a positive-definite stress, else CSH_ERR_NONPHYSICAL with the
+ * handle still returned).  The handle allocates a workspace of
+ * 480 (nx + 2)(ny + 2)(nz + 2) bytes for the face states.  stream: the HIP
+ * stream all work of the handle runs on (NULL: the null stream).
+ */
+int csh3_init_state(csh3_grid **h, int nx, int ny, int nz, double dx, double dy, double dz, int bc_x, int bc_y,
+                    int bc_z, const void *W, void *U, void *stream);
+
+/* One step with a host timestep: U -> U_new (distinct buffers).  Synchronises;
+ * CSH_ERR_NONPHYSICAL if the new state is not physical. */
+int csh3_step(csh3_grid *h, double dt, const void *U, void *U_new);
+
+/* Largest CFL rate of U (dt = C / s).  Synchronises. */
+int csh3_max_signal_speed(csh3_grid *h, const void *U, double *s);
+
+/* The CFL rate of the output of the last step, reduced inside that step. */
+int csh3_last_signal_speed(csh3_grid *h, double *s);
+
+/* nsteps steps with dt = cfl / s chosen on the device from each step's input,
+ * replayed from a captured HIP graph (recorded once per argument set).  U is
+ * advanced in place, U_work is scratch of the same size, dt_log (device,
+ * nsteps doubles) receives the timesteps.  Synchronises. */
+int csh3_run_cfl(csh3_grid *h, int nsteps, double cfl, void *U, void *U_work, double *dt_log);
+
+/* Free the handle (NULL is ignored). */
+void csh3_destroy(csh3_grid *h);
+
 #ifdef __cplusplus
 }
 #endif

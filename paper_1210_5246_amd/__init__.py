@@ -45,6 +45,15 @@ _dp = ctypes.POINTER(ctypes.c_double)
 # (name, restype, argtypes) of every exported entry point
 _SIGNATURES = [
     ("csh_last_error", ctypes.c_char_p, []),
+    ("csh3_last_error", ctypes.c_char_p, []),
+    ("csh3_init_state", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
+    ("csh3_step", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp]),
+    ("csh3_max_signal_speed", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    ("csh3_last_signal_speed", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    ("csh3_run_cfl", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp]),
+    ("csh3_destroy", None, [_vp]),
     ("csh_init_state", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     ("csh_set_state", ctypes.c_int, [_vp, _vp, _vp]),
@@ -232,6 +241,68 @@ class Grid:
         _check(lib().csh_init_state_adjoint(self._h, _dev(W, self.dtype), _dev(lam_U, self.dtype),
                                             _dev(out, self.dtype)))
         return out
+
+
+def _check3(code: int):
+    if code != CSH_OK:
+        msg = lib().csh3_last_error().decode(errors="replace")
+        if code == CSH_ERR_NONPHYSICAL:
+            raise NonPhysicalState(code, msg)
+        raise CshError(code, msg)
+
+
+class Grid3:
+    """A 3-D handle (``csh3_grid``) plus the conserved state ``U`` [10, nz, ny, nx].
+
+    ``W``: primitive fields (rho, u, v, w, Pxx, Pxy, Pxz, Pyy, Pyz, Pzz) as a
+    contiguous float64 GPU tensor [10, nz, ny, nx]; ``h`` = (dx, dy, dz).
+    """
+
+    def __init__(self, W: torch.Tensor, h, bc=(BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)):
+        if W.dim() != 4 or W.shape[0] != 10:
+            raise ValueError("W must be [10, nz, ny, nx]")
+        self.nz, self.ny, self.nx = (int(x) for x in W.shape[1:])
+        self.h = tuple(float(x) for x in h)
+        self.U = torch.empty_like(W)
+        self._h = _vp()
+        _check3(lib().csh3_init_state(ctypes.byref(self._h), self.nx, self.ny, self.nz, *self.h, int(bc[0]),
+                                      int(bc[1]), int(bc[2]), _dev(W, torch.float64),
+                                      _dev(self.U, torch.float64), _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.csh3_destroy(h)
+            self._h = None
+
+    def step(self, dt: float, U: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+        U = self.U if U is None else U
+        out = torch.empty_like(U) if out is None else out
+        _check3(lib().csh3_step(self._h, float(dt), _dev(U, torch.float64), _dev(out, torch.float64)))
+        return out
+
+    def max_signal_speed(self, U: torch.Tensor | None = None) -> float:
+        U = self.U if U is None else U
+        s = ctypes.c_double()
+        _check3(lib().csh3_max_signal_speed(self._h, _dev(U, torch.float64), ctypes.byref(s)))
+        return s.value
+
+    def last_signal_speed(self) -> float:
+        s = ctypes.c_double()
+        _check3(lib().csh3_last_signal_speed(self._h, ctypes.byref(s)))
+        return s.value
+
+    def run_cfl(self, nsteps: int, cfl: float = 0.8) -> torch.Tensor:
+        """Advance ``self.U`` in place by ``nsteps`` device-timed steps; returns the timesteps."""
+        work = getattr(self, "_work", None)
+        if work is None:
+            work = self._work = torch.empty_like(self.U)
+        log = getattr(self, "_log", None)
+        if log is None or log.numel() < max(nsteps, 1):
+            log = self._log = torch.empty(max(nsteps, 1), dtype=torch.float64, device=self.U.device)
+        _check3(lib().csh3_run_cfl(self._h, int(nsteps), float(cfl), _dev(self.U, torch.float64),
+                                   _dev(work, torch.float64), _dev(log, torch.float64)))
+        return log[:nsteps]
 
 
 def init_state(W: torch.Tensor, dx: float, dy: float = 1.0, bc=(BC_PERIODIC, BC_PERIODIC)) -> Grid:

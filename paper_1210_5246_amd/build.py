@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcshydro.so")
-SOURCES = ["csh_api.hip", "csh_fwd.hip", "csh_kt.hip", "csh_diag.hip", "csh_batch.hip", "csh_adjoint.hip"]
+SOURCES = ["csh_api.hip", "csh_fwd.hip", "csh_kt.hip", "csh_diag.hip", "csh3.hip", "csh_batch.hip", "csh_adjoint.hip"]
 ARCH = os.environ.get("CSH_OFFLOAD_ARCH", "gfx950")
 
 

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "cshydro.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(csh_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(csh3?_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -38,6 +38,10 @@ def test_argument_validation_without_gpu():
     assert L.csh_init_state(ctypes.byref(h), 4, 4, -1.0, 1.0, 0, 0, 0, None, None, None) == csh.CSH_ERR_ARG
     assert L.csh_step(None, 0.1, None, None) == csh.CSH_ERR_ARG
     assert L.csh_batch_init(ctypes.byref(h), 0, None, 0, None, None, None) == csh.CSH_ERR_ARG
+    assert L.csh3_init_state(ctypes.byref(h), 4, 0, 4, 1.0, 1.0, 1.0, 0, 0, 0, None, None, None) == csh.CSH_ERR_ARG
+    assert b"nz" in L.csh3_last_error()
+    assert L.csh3_init_state(ctypes.byref(h), 4, 4, 4, 1.0, 0.0, 1.0, 0, 0, 0, None, None, None) == csh.CSH_ERR_ARG
+    assert L.csh3_step(None, 0.1, None, None) == csh.CSH_ERR_ARG
 
 
 def _sources(folder, exts):
