@@ -42,6 +42,18 @@ def test_argument_validation_without_gpu():
     assert b"nz" in L.csh3_last_error()
     assert L.csh3_init_state(ctypes.byref(h), 4, 4, 4, 1.0, 0.0, 1.0, 0, 0, 0, None, None, None) == csh.CSH_ERR_ARG
     assert L.csh3_step(None, 0.1, None, None) == csh.CSH_ERR_ARG
+    # the largest grids: one plane of the state must stay below 4 GiB (32-bit
+    # offsets); the limit is checked before any device work
+    assert L.csh_init_state(ctypes.byref(h), 1 << 15, 1 << 14, 1.0, 1.0, 0, 0, 0, None, None, None) == csh.CSH_ERR_ARG
+    assert b"4 GiB" in L.csh_last_error()
+    assert L.csh_init_state(ctypes.byref(h), 1 << 16, 1 << 14, 1.0, 1.0, 0, 0, 1, None, None, None) == csh.CSH_ERR_ARG
+    assert b"4 GiB" in L.csh_last_error()
+    # just below the limit the size passes and the missing buffers are reported
+    assert L.csh_init_state(ctypes.byref(h), 1 << 15, 1 << 14, 1.0, 1.0, 0, 0, 1, None, None, None) == csh.CSH_ERR_ARG
+    assert b"device pointers" in L.csh_last_error()
+    assert L.csh3_init_state(ctypes.byref(h), 1024, 1024, 512, 1.0, 1.0, 1.0, 0, 0, 0, None, None, None) == \
+        csh.CSH_ERR_ARG
+    assert b"4 GiB" in L.csh3_last_error()
 
 
 def _sources(folder, exts):
