@@ -27,10 +27,10 @@ BYTES_PER_CELL_F32 = 48
 BYTES_PER_CELL_KT_F64 = 240
 KT_CFL = 0.8
 # 3-D: 10 planes read + 10 written = 160 B per cell-update for a single pass;
-# the two-kernel design also writes six face states (480 B) and reads them
-# twice (960 B): 1600 B
+# the z-march also writes the two y-face states (160 B) and the partial update
+# (80 B), which the second kernel reads back: 640 B
 BYTES_PER_CELL_3D_MIN = 160
-BYTES_PER_CELL_3D_DESIGN = 1600
+BYTES_PER_CELL_3D_DESIGN = 640
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 

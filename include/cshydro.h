@@ -266,7 +266,7 @@ const char *csh3_last_error(void);
  * Create a 3-D handle and convert W to U (validation as csh_init_state:
  * rho > 0 and a positive-definite stress, else CSH_ERR_NONPHYSICAL with the
  * handle still returned).  The handle allocates a workspace of
- * 480 (nx + 2)(ny + 2)(nz + 2) bytes for the face states.  stream: the HIP
+ * 160 nx (ny + 2) nz bytes for the y-face states of a step.  stream: the HIP
  * stream all work of the handle runs on (NULL: the null stream).
  */
 int csh3_init_state(csh3_grid **h, int nx, int ny, int nz, double dx, double dy, double dz, int bc_x, int bc_y,

@@ -1,18 +1,22 @@
 // Three-dimensional sweep of the ten-moment system (FP64), gfx950.
 //
 // Two launches per step:
-//   trace3_kernel  one thread per cell of the grid and of a one-cell ring
-//                  around it: primitive state and its six neighbours (index
-//                  maps of the boundary conditions), characteristic MC slopes
-//                  along x, y, z, the Hancock predictor with the transverse
-//                  terms of the two other axes, the six face states, stored
-//                  as [6 faces][10][ring-extended cells];
-//   flux3_kernel   one thread per cell: HLL fluxes of its six faces from its
-//                  own face states and its neighbours' (each face is solved by
-//                  both cells that share it), the unsplit update and the fused
-//                  CFL reduction that sets the next timestep on the device.
-// This moves about 1.7 KB per cell-update (the face states are written once
-// and read twice) against 160 B for a single-pass kernel.
+//   march3_kernel  a wavefront per 60-column strip of one row y (the rows
+//                  -1 and ny included, for their y-face states), marching
+//                  along z over a segment of planes with two planes of
+//                  primitive states in registers; per cell the
+//                  characteristic MC slopes along x (lane shifts), y (the
+//                  neighbouring rows, loaded) and z, the Hancock predictor
+//                  with the transverse terms of the two other axes, the six
+//                  face states; the x-face flux by a lane shift and the z-face
+//                  flux against the previous plane's high face, so the
+//                  partial update U - dt/dx dFx - dt/dz dFz is written to
+//                  the output; the two y-face states go to a workspace
+//                  [2][10][nz][ny + 2][nx];
+//   yflux3_kernel  a thread per (x, z) column marching over a segment of
+//                  rows: each y-face HLL flux once, the end of the update and
+//                  the fused CFL reduction that sets the next timestep on the
+//                  device.
 #include "csh3_device.h"
 #include "csh_internal.h"
 #include "cshydro.h"
@@ -67,73 +71,167 @@ __device__ __forceinline__ V10 load_prim(const Args& p, int i, int j, int k)
     return to_prim(U, rcp(U.v[0]));
 }
 
-template <int N>
-__device__ __forceinline__ void axis_slope(const Args& p, const V10& w, double ir, int i, int j, int k, V10& dw,
-                                           V10& base, double kf)
+// wavefront-wide shift of a 10-vector by one lane (zero fill at the end)
+template <int D>
+__device__ __forceinline__ V10 shift(const V10& x)
 {
-    const int di = N == 0, dj = N == 1, dk = N == 2;
-    const V10 wm = load_prim(p, i - di, j - dj, k - dk), wp = load_prim(p, i + di, j + dj, k + dk);
-    const Eig<N> e = eig<N>(w, ir);
-    dw = limited_slope<N>(w, e, wm, wp);
-    const V10 Ad = jac<N>(w, ir, dw);
+    V10 y;
 #pragma unroll
-    for (int m = 0; m < NV; ++m) base.v[m] -= kf * Ad.v[m];
+    for (int m = 0; m < NV; ++m) y.v[m] = lane_shift<D>(x.v[m]);
+    return y;
 }
 
-template <int N>
-__device__ __forceinline__ void store_faces(const Args& p, size_t ne, size_t e, const V10& w, const V10& base,
-                                            const V10& dw, double kf)
+struct MArgs {
+    Args a;
+    double* FY;        // y-face states [2 (lo, hi)][10][nz][ny + 2][nx]
+    int nstrips, nsegs, tz;
+};
+
+// One wavefront: 60 output columns (64 lanes, 2 halo lanes per side) of one
+// row j in [-1, ny] (the two outer rows only supply y-face states), marching
+// over planes [z0, z1).  Per plane: characteristic slopes along x (lane
+// shifts), y (the neighbouring rows, loaded) and z (three planes in
+// registers), the six face states, the x-face flux by a lane shift, the
+// z-face flux against the previous plane's high face; the partial update
+// U - dt/dx dFx - dt/dz dFz is written to Unew and the two y-face states to FY.
+__global__ __launch_bounds__(256) void march3_kernel(MArgs q)
 {
-    const double a = 1.7320508075688772935 * sqrt(w.v[P(N, N)] * rcp(w.v[0]));
-    const double chi = 0.5 + kf * fmin(w.v[1 + N] + a, 0.0);
-    const double clo = 0.5 - kf * fmax(w.v[1 + N] - a, 0.0);
-    double* lo = p.FS + (size_t)(2 * N) * NV * ne + e;
-    double* hi = lo + (size_t)NV * ne;
+    const Args& p = q.a;
+    double t_now;
+    const double dt = step_dt(p, &t_now);
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.slots[p.s_out].s_bits = 0ull;
+    const int lane = threadIdx.x & 63;
+    const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ey = p.n[1] + 2;
+    if (wid >= (long)q.nsegs * q.nstrips * ey) return;  // uniform per wavefront
+    const int jj = (int)(wid % ey), sx = (int)((wid / ey) % q.nstrips), sz = (int)(wid / ((long)ey * q.nstrips));
+    const int j = jj - 1;
+    const bool interior = j >= 0 && j < p.n[1];
+    const int c = sx * kStrip - 2 + lane;
+    const bool own = lane >= 2 && lane < 2 + kStrip && c < p.n[0];
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int gc = map_index(c, nx, p.bc[0]);
+    const int gjm = map_index(j - 1, ny, p.bc[1]), gj0 = map_index(j, ny, p.bc[1]), gjp = map_index(j + 1, ny, p.bc[1]);
+    const size_t plane = (size_t)nx * ny, ncell = plane * nz;
+    const size_t fplane = (size_t)nx * ey, nf = fplane * nz;
+    const double kx = 0.5 * dt / p.h[0], ky = 0.5 * dt / p.h[1], kz = 0.5 * dt / p.h[2];
+    const double cx = dt / p.h[0], cz = dt / p.h[2];
+    const int z0 = sz * q.tz, z1 = min(z0 + q.tz, nz);
+
+    auto cell = [&](int gj, int r) -> size_t {
+        return ((size_t)map_index(r, nz, p.bc[2]) * ny + gj) * nx + gc;
+    };
+    auto ld = [&](int gj, int r) -> V10 { return load(p.U, ncell, cell(gj, r)); };
+    auto prim = [](const V10& U) -> V10 { return to_prim(U, rcp(U.v[0])); };
+
+    // Window of the first step (r = z0 - 1): primitive planes z0 - 2 and
+    // z0 - 1, the conserved centre of plane z0 - 1, and the loads the step
+    // consumes, issued one step ahead (centre of plane r + 1, rows j -+ 1 of
+    // plane r): one wavefront per SIMD hides the memory latency this way.
+    V10 Wa = prim(ld(gj0, z0 - 2)), C0 = ld(gj0, z0 - 1), Wb = prim(C0);
+    V10 Cz = ld(gj0, z0), Cym = ld(gjm, z0 - 1), Cyp = ld(gjp, z0 - 1), zhi_prev, acc;
 #pragma unroll
-    for (int m = 0; m < NV; ++m) {
-        lo[m * ne] = base.v[m] - clo * dw.v[m];
-        hi[m * ne] = base.v[m] + chi * dw.v[m];
+    for (int m = 0; m < NV; ++m) zhi_prev.v[m] = acc.v[m] = 0.0;
+
+    // plane r: Wm = plane r - 1 (refilled with plane r + 1), W0 = plane r.
+    // Ordered so that each slope and face pair dies as early as possible.
+    auto plane_step = [&](int r, V10& Wm, const V10& W0) {
+        // the next step's loads first
+        const V10 Cz_n = ld(gj0, r + 2), Cym_n = ld(gjm, r + 1), Cyp_n = ld(gjp, r + 1);
+        const double ir = rcp(W0.v[0]);
+        const double a = 1.7320508075688772935 * sqrt(ir);
+        auto coef = [&](int k, double kf, double& chi, double& clo) {
+            const double ak = a * sqrt(W0.v[P(k, k)]), uk = W0.v[1 + k];
+            chi = 0.5 + kf * fmin(uk + ak, 0.0);
+            clo = 0.5 - kf * fmax(uk - ak, 0.0);
+        };
+        V10 base = W0, dz, dy, dx;
+        {
+            const Eig<0> e = eig<0>(W0, ir);
+            dx = limited_slope<0>(W0, e, shift<-1>(W0), shift<+1>(W0));
+            const V10 Ad = jac<0>(W0, ir, dx);
+#pragma unroll
+            for (int m = 0; m < NV; ++m) base.v[m] -= kx * Ad.v[m];
+        }
+        {
+            const Eig<1> e = eig<1>(W0, ir);
+            dy = limited_slope<1>(W0, e, prim(Cym), prim(Cyp));
+            const V10 Ad = jac<1>(W0, ir, dy);
+#pragma unroll
+            for (int m = 0; m < NV; ++m) base.v[m] -= ky * Ad.v[m];
+        }
+        const V10 Wp = prim(Cz);
+        {
+            const Eig<2> e = eig<2>(W0, ir);
+            dz = limited_slope<2>(W0, e, Wm, Wp);
+            const V10 Ad = jac<2>(W0, ir, dz);
+#pragma unroll
+            for (int m = 0; m < NV; ++m) base.v[m] -= kz * Ad.v[m];
+        }
+        double ch, cl;
+        if (r >= z0 && r < z1 && own) {  // the y-face states of (c, j, r)
+            coef(1, ky, ch, cl);
+            const size_t f = ((size_t)r * ey + jj) * nx + c;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                q.FY[m * nf + f] = base.v[m] - cl * dy.v[m];
+                q.FY[(NV + m) * nf + f] = base.v[m] + ch * dy.v[m];
+            }
+        }
+        coef(2, kz, ch, cl);
+        V10 zhi;
+        if (r >= z0) {
+            V10 zlo;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) zlo.v[m] = base.v[m] - cl * dz.v[m];
+            const V10 Gz = hll<2>(zhi_prev, zlo);  // face r - 1/2
+            if (r > z0 && interior && own) {
+#pragma unroll
+                for (int m = 0; m < NV; ++m)
+                    p.Unew[m * ncell + ((size_t)(r - 1) * ny + j) * nx + c] = acc.v[m] - cz * Gz.v[m];
+            }
+            if (r < z1) {
+#pragma unroll
+                for (int m = 0; m < NV; ++m) acc.v[m] = C0.v[m] + cz * Gz.v[m];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NV; ++m) zhi.v[m] = base.v[m] + ch * dz.v[m];
+        zhi_prev = zhi;
+        if (r >= z0 && r < z1) {
+            coef(0, kx, ch, cl);
+            V10 xlo, xhi;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                xlo.v[m] = base.v[m] - cl * dx.v[m];
+                xhi.v[m] = base.v[m] + ch * dx.v[m];
+            }
+            const V10 F = hll<0>(xhi, shift<+1>(xlo));  // face c + 1/2
+            const V10 Fm = shift<-1>(F);
+#pragma unroll
+            for (int m = 0; m < NV; ++m) acc.v[m] -= cx * (F.v[m] - Fm.v[m]);
+        }
+        // advance the window: plane r + 1 takes the place of plane r - 1
+        Wm = Wp;
+        C0 = Cz;
+        Cz = Cz_n;
+        Cym = Cym_n;
+        Cyp = Cyp_n;
+    };
+
+    for (int r = z0 - 1; r <= z1; r += 2) {
+        plane_step(r, Wa, Wb);
+        if (r + 1 > z1) break;
+        plane_step(r + 1, Wb, Wa);
     }
 }
 
-__global__ __launch_bounds__(256) void trace3_kernel(Args p)
+// A thread per (x, z) column marching over a segment of rows: each y face's
+// flux once (the previous face's flux carried in registers), the end of the
+// update, CFL rate and validity.
+__global__ __launch_bounds__(256) void yflux3_kernel(MArgs q, int ty)
 {
-    const int ex = p.n[0] + 2, ey = p.n[1] + 2, ez = p.n[2] + 2;
-    const size_t ne = (size_t)ex * ey * ez;
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ne) return;
-    double t_now;
-    const double dt = step_dt(p, &t_now);
-    if (e == 0) p.slots[p.s_out].s_bits = 0ull;  // the flux kernel accumulates the new rate there
-    const int i = (int)(e % ex) - 1, j = (int)((e / ex) % ey) - 1, k = (int)(e / ((size_t)ex * ey)) - 1;
-    const V10 w = load_prim(p, i, j, k);
-    const double ir = rcp(w.v[0]);
-    const double kf0 = 0.5 * dt / p.h[0], kf1 = 0.5 * dt / p.h[1], kf2 = 0.5 * dt / p.h[2];
-    V10 base = w, d0, d1, d2;
-    axis_slope<0>(p, w, ir, i, j, k, d0, base, kf0);
-    axis_slope<1>(p, w, ir, i, j, k, d1, base, kf1);
-    axis_slope<2>(p, w, ir, i, j, k, d2, base, kf2);
-    store_faces<0>(p, ne, e, w, base, d0, kf0);
-    store_faces<1>(p, ne, e, w, base, d1, kf1);
-    store_faces<2>(p, ne, e, w, base, d2, kf2);
-}
-
-__device__ __forceinline__ V10 load_face(const Args& p, size_t ne, int face, size_t e)
-{
-    return load(p.FS + (size_t)face * NV * ne, ne, e);
-}
-
-template <int N>
-__device__ __forceinline__ void axis_flux(const Args& p, size_t ne, size_t e, size_t stride, double c, V10& du)
-{
-    const V10 Fm = hll<N>(load_face(p, ne, 2 * N + 1, e - stride), load_face(p, ne, 2 * N, e));
-    const V10 Fp = hll<N>(load_face(p, ne, 2 * N + 1, e), load_face(p, ne, 2 * N, e + stride));
-#pragma unroll
-    for (int m = 0; m < NV; ++m) du.v[m] -= c * (Fp.v[m] - Fm.v[m]);
-}
-
-__global__ __launch_bounds__(256) void flux3_kernel(Args p)
-{
+    const Args& p = q.a;
     double t_now;
     const double dt = step_dt(p, &t_now);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -141,32 +239,44 @@ __global__ __launch_bounds__(256) void flux3_kernel(Args p)
         p.slots[p.s_reset].s_bits = 0ull;
         if (p.dt_log) *p.dt_log = dt;
     }
-    const size_t ncell = (size_t)p.n[0] * p.n[1] * p.n[2];
-    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2], ey = ny + 2;
+    const int nseg = (ny + ty - 1) / ty;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     double smax = 0.0;
     bool bad = false;
-    if (c < ncell) {
-        const int i = (int)(c % p.n[0]), j = (int)((c / p.n[0]) % p.n[1]), k = (int)(c / ((size_t)p.n[0] * p.n[1]));
-        const int ex = p.n[0] + 2, ey = p.n[1] + 2;
-        const size_t ne = (size_t)ex * ey * (p.n[2] + 2);
-        const size_t e = ((size_t)(k + 1) * ey + (j + 1)) * ex + (i + 1);
-        V10 du;
-#pragma unroll
-        for (int m = 0; m < NV; ++m) du.v[m] = 0.0;
-        axis_flux<0>(p, ne, e, 1, dt / p.h[0], du);
-        axis_flux<1>(p, ne, e, (size_t)ex, dt / p.h[1], du);
-        axis_flux<2>(p, ne, e, (size_t)ex * ey, dt / p.h[2], du);
-        const V10 U = load(p.U, ncell, c);
-        V10 Un;
-#pragma unroll
-        for (int m = 0; m < NV; ++m) {
-            Un.v[m] = U.v[m] + du.v[m];
-            p.Unew[m * ncell + c] = Un.v[m];
-        }
-        const V10 wn = to_prim(Un, rcp(Un.v[0]));
+    if (t < (size_t)nx * nz * nseg) {
+        const int i = (int)(t % nx), k = (int)((t / nx) % nz), sy = (int)(t / ((size_t)nx * nz));
+        const int y0 = sy * ty, y1 = min(y0 + ty, ny);
+        const size_t ncell = (size_t)nx * ny * nz, nf = (size_t)nx * ey * nz;
+        const double cy = dt / p.h[1];
         const double ih[3] = {1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2]};
-        smax = signal_rate(wn, ih);
-        bad = !physical(wn);
+        auto fidx = [&](int jj) { return ((size_t)k * ey + jj) * nx + i; };  // jj = j + 1
+        const double* FL = q.FY;
+        const double* FH = q.FY + (size_t)NV * nf;
+        // face y0 - 1/2: high state of row y0 - 1, low state of row y0; the
+        // face states of the next face are loaded one row ahead
+        V10 Gm = hll<1>(load(FH, nf, fidx(y0)), load(FL, nf, fidx(y0 + 1)));
+        V10 hi_n = load(FH, nf, fidx(y0 + 1)), lo_n = load(FL, nf, fidx(y0 + 2));
+        for (int j = y0; j < y1; ++j) {
+            const V10 hi = hi_n, lo = lo_n;
+            if (j + 1 < y1) {
+                hi_n = load(FH, nf, fidx(j + 2));
+                lo_n = load(FL, nf, fidx(j + 3));
+            }
+            const size_t c = ((size_t)k * ny + j) * nx + i;
+            const V10 A = load(p.Unew, ncell, c);
+            const V10 Gp = hll<1>(hi, lo);
+            V10 Un;
+#pragma unroll
+            for (int m = 0; m < NV; ++m) {
+                Un.v[m] = A.v[m] - cy * (Gp.v[m] - Gm.v[m]);
+                p.Unew[m * ncell + c] = Un.v[m];
+            }
+            const V10 wn = to_prim(Un, rcp(Un.v[0]));
+            smax = fmax(smax, signal_rate(wn, ih));
+            bad = bad || !physical(wn);
+            Gm = Gp;
+        }
     }
     smax = wave_max(smax);
     if ((threadIdx.x & 63) == 0) atomic_max_pos(&p.slots[p.s_out].s_bits, smax);
@@ -218,7 +328,7 @@ struct csh3_grid {
     hipStream_t capture = nullptr;
     Slot* slots = nullptr;
     int* flag = nullptr;
-    double* FS = nullptr;
+    double* FS = nullptr;  // y-face states of the march
     int phase = 0;
     hipGraphExec_t exec = nullptr;
     int g_nsteps = -1;
@@ -247,9 +357,10 @@ size_t ncell(const csh3_grid* h)
     return (size_t)h->n[0] * h->n[1] * h->n[2];
 }
 
-size_t next(const csh3_grid* h)
+// cells of the y-face workspace: the grid plus one row on each side in y
+size_t nfy(const csh3_grid* h)
 {
-    return (size_t)(h->n[0] + 2) * (h->n[1] + 2) * (h->n[2] + 2);
+    return (size_t)h->n[0] * (h->n[1] + 2) * h->n[2];
 }
 
 d3::Args args(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, double cfl, double* log,
@@ -277,14 +388,31 @@ d3::Args args(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, 
     return a;
 }
 
+// z-segment length of the march: about 32 planes, at least 4 segments'
+// worth of wavefronts per SIMD on small grids is not needed (the y rows and
+// x strips already give thousands)
+int planes_per_segment(const csh3_grid* h)
+{
+    const int nz = h->n[2];
+    const int nseg = std::max(1, (nz + 31) / 32);
+    return (nz + nseg - 1) / nseg;
+}
+
 hipError_t enqueue_step3(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, double cfl, double* log,
                          hipStream_t s)
 {
-    const d3::Args a = args(h, U, Un, dev_dt, dt, cfl, log, nullptr);
-    h->phase = a.s_out;
-    const size_t ne = next(h), nc = ncell(h);
-    d3::trace3_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(a);
-    d3::flux3_kernel<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(a);
+    d3::MArgs m{};
+    m.a = args(h, U, Un, dev_dt, dt, cfl, log, nullptr);
+    m.FY = h->FS;
+    m.nstrips = (h->n[0] + csh::kStrip - 1) / csh::kStrip;
+    m.tz = planes_per_segment(h);
+    m.nsegs = (h->n[2] + m.tz - 1) / m.tz;
+    h->phase = m.a.s_out;
+    const long nwaves = (long)m.nsegs * m.nstrips * (h->n[1] + 2);
+    const int ty = 32, nsegy = (h->n[1] + ty - 1) / ty;
+    const size_t ncol = (size_t)h->n[0] * h->n[2] * nsegy;
+    d3::march3_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(m);
+    d3::yflux3_kernel<<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(m, ty);
     return hipGetLastError();
 }
 
@@ -333,8 +461,8 @@ extern "C" int csh3_init_state(csh3_grid** out, int nx, int ny, int nz, double d
     if (!out) return fail3(CSH_ERR_ARG, "h is NULL");
     *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1) return fail3(CSH_ERR_ARG, "nx, ny, nz must be >= 1");
-    if ((long long)(nx + 2) * (ny + 2) * (nz + 2) * 8 >= (1LL << 32))
-        return fail3(CSH_ERR_ARG, "one extended plane must be smaller than 4 GiB");
+    if ((long long)nx * (ny + 2) * nz * 8 >= (1LL << 32))
+        return fail3(CSH_ERR_ARG, "one plane of the state must be smaller than 4 GiB");
     if (!(dx > 0) || !(dy > 0) || !(dz > 0)) return fail3(CSH_ERR_ARG, "cell sizes must be > 0");
     const int bcs[3] = {bc_x, bc_y, bc_z};
     for (int k = 0; k < 3; ++k)
@@ -354,7 +482,7 @@ extern "C" int csh3_init_state(csh3_grid** out, int nx, int ny, int nz, double d
         return code;
     };
     if (hipMalloc(&h->slots, 3 * sizeof(Slot)) != hipSuccess || hipMalloc(&h->flag, sizeof(int)) != hipSuccess ||
-        hipMalloc(&h->FS, sizeof(double) * 6 * d3::NV * next(h)) != hipSuccess)
+        hipMalloc(&h->FS, sizeof(double) * 2 * d3::NV * nfy(h)) != hipSuccess)
         return cleanup(fail3(CSH_ERR_HIP, "hipMalloc of the handle's buffers failed"));
     if (hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
         return cleanup(fail3(CSH_ERR_HIP, "hipStreamCreate failed"));
