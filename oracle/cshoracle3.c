@@ -263,15 +263,11 @@ void orc3_hll(int n, const double wl[N3], const double wr[N3], double flux[N3])
     }
 }
 
+/* ghost index maps: periodic wrap, or the nearest edge cell (zero gradient) */
 static int map3(int i, int n, int bc)
 {
-    if (bc == ORC_BC_PERIODIC) {
-        int r = i % n;
-        return (r < 0) ? r + n : r;
-    }
-    if (i < 0) return 0;
-    if (i >= n) return n - 1;
-    return i;
+    if (bc == ORC_BC_PERIODIC) return ((i % n) + n) % n;
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
 static int grid3_ok(const orc_grid3 *g)

@@ -99,12 +99,13 @@ MUTANTS = {
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_fails_a_pin(name, tmp_path):
     old, new = MUTANTS[name]
+    # the site must be unique within a file; a statement the 2-D and 3-D
+    # oracles share is planted in both
     srcs = {p: open(p).read() for p in (SRC, SRC3)}
-    hits = [p for p, t in srcs.items() if t.count(old) == 1]
-    assert len(hits) == 1 and sum(t.count(old) for t in srcs.values()) == 1, \
+    assert all(t.count(old) <= 1 for t in srcs.values()) and any(t.count(old) for t in srcs.values()), \
         f"mutation site not found uniquely: {name}"
     for p, t in srcs.items():
-        (tmp_path / os.path.basename(p)).write_text(t.replace(old, new) if p == hits[0] else t)
+        (tmp_path / os.path.basename(p)).write_text(t.replace(old, new))
     for h in ("cshoracle.h",):
         (tmp_path / h).write_text(open(os.path.join(ROOT, "oracle", h)).read())
     lib = tmp_path / "libmut.so"
