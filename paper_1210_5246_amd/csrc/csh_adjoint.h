@@ -117,20 +117,20 @@ CSH_HD void backproject_vjp(const P& w, const E& e, const A6& al, const P& db, P
 }
 
 // MC: m = sgn(dc) min(2|dl|, |dc|, 2|dr|) if dl and dr are nonzero with one
-// sign, else 0 (the forward form tests the signs, not the product)
+// sign, else 0 (the forward form tests the signs, not the product).  The
+// branch taken sets the weights of the two inputs (0.5 / 0.5 centred, 2 / 0
+// or 0 / 2 one-sided, 0 / 0 off); written without branches so the two
+// adjoints stay in registers.
 CSH_HD void mc_vjp(double dl, double dr, double mb, double& dlb, double& drb)
 {
-    if (dl == 0.0 || dr == 0.0 || (dl < 0.0) != (dr < 0.0)) return;
-    const double dc = 0.5 * (dl + dr);
-    const double adc = fabs(dc), al2 = 2.0 * fabs(dl), ar2 = 2.0 * fabs(dr);
-    if (adc <= al2 && adc <= ar2) {  // centred difference
-        dlb += 0.5 * mb;
-        drb += 0.5 * mb;
-    } else if (al2 <= ar2) {          // 2 dl (same sign as dc)
-        dlb += 2.0 * mb;
-    } else {
-        drb += 2.0 * mb;
-    }
+    const bool on = dl != 0.0 && dr != 0.0 && (dl < 0.0) == (dr < 0.0);
+    const double adc = fabs(0.5 * (dl + dr)), al2 = 2.0 * fabs(dl), ar2 = 2.0 * fabs(dr);
+    const bool cen = adc <= al2 && adc <= ar2;  // centred difference
+    const bool left = al2 <= ar2;               // else 2 dl (same sign as dc), else 2 dr
+    const double wl = on ? (cen ? 0.5 : (left ? 2.0 : 0.0)) : 0.0;
+    const double wr = on ? (cen ? 0.5 : (left ? 0.0 : 2.0)) : 0.0;
+    dlb += wl * mb;
+    drb += wr * mb;
 }
 
 // limited_slope(w, e, dl, dr) -> dm
@@ -178,9 +178,75 @@ CSH_HD void jac_vjp(const P& w, double ir, const P& d, const P& ob, P& wb, doubl
 CSH_HD P swapb(const P& a) { return swap(a); }  // the adjoint of a permutation that is its own inverse
 
 // face_states<TWOD>(W0, Wl, Wr, Wm, Wp, kx, ky): adjoints of the five input states
+// The reverse pass of face_states in two parts that add up to it: the y part
+// (the y slope, its tracing coefficients and transverse term; adjoints of Wm,
+// Wp and its share of W0) and the x part (the rest: the x slope, its
+// coefficients and term, and the identity part of base; Wl, Wr and the rest of
+// W0).  Both need the summed face adjoints of base; each adds its own 1/rho
+// term.  W0b accumulates y first, then x.
+CSH_HD P base_adjoint(const Faces<double>& fb, bool twod)
+{
+    P baseb = zero_p();
+    // xhi = base + chix dxm ; xlo = base - clox dxm ; the same for y
+    acc(baseb, fb.xhi);
+    acc(baseb, fb.xlo);
+    if (twod) {
+        acc(baseb, fb.yhi);
+        acc(baseb, fb.ylo);
+    }
+    return baseb;
+}
+
+CSH_HD void face_states_vjp_y(const P& W0, const P& Wm, const P& Wp, double ky, const Faces<double>& fb, P& W0b,
+                              P& Wmb, P& Wpb)
+{
+    // ---- forward recompute ----
+    const double ir = rcp(W0.r);
+    const P W0s = swap(W0);
+    const E ey = eig_x(W0s, ir);
+    const P dlys = swap(sub(W0, Wm)), drys = swap(sub(Wp, W0));
+    const P dyms = limited_slope(W0s, ey, dlys, drys);
+    const P dym = swap(dyms);
+    const double chiy = 0.5 + ky * fmin(W0.v + ey.a, 0.0);
+    const double cloy = 0.5 - ky * fmax(W0.v - ey.a, 0.0);
+    // ---- reverse ----
+    const P baseb = base_adjoint(fb, true);
+    double irb = 0.0;
+    E eyb{0, 0, 0, 0, 0, 0};
+    P dymb = zero_p();
+    acc(dymb, scale(chiy, fb.yhi));
+    acc(dymb, scale(-cloy, fb.ylo));
+    const double chiyb = dot(dym, fb.yhi), cloyb = -dot(dym, fb.ylo);
+    // chiy = 1/2 + ky min(v + ay, 0) ; cloy = 1/2 - ky max(v - ay, 0)
+    if (W0.v + ey.a < 0.0) {
+        W0b.v += ky * chiyb;
+        eyb.a += ky * chiyb;
+    }
+    if (W0.v - ey.a > 0.0) {
+        W0b.v -= ky * cloyb;
+        eyb.a += ky * cloyb;
+    }
+    // base -= ky swap(jac_x(W0s, ir, dyms))
+    P W0sb = zero_p(), dymsb = swapb(dymb);
+    jac_vjp(W0s, ir, dyms, scale(-ky, swapb(baseb)), W0sb, irb, dymsb);
+    // dyms = limited_slope(W0s, ey, dlys, drys)
+    P dlysb = zero_p(), drysb = zero_p();
+    limited_slope_vjp(W0s, ey, dlys, drys, dymsb, W0sb, eyb, dlysb, drysb);
+    eig_vjp(W0s, ir, ey, eyb, W0sb, irb);
+    acc(W0b, swapb(W0sb));
+    // dlys = swap(W0 - Wm), drys = swap(Wp - W0)
+    const P dlyb = swapb(dlysb), dryb = swapb(drysb);
+    acc(W0b, dlyb);
+    acc(Wmb, scale(-1.0, dlyb));
+    acc(Wpb, dryb);
+    acc(W0b, scale(-1.0, dryb));
+    // ir = 1 / W0.r
+    W0b.r += -ir * ir * irb;
+}
+
 template <bool TWOD>
-CSH_HD void face_states_vjp(const P& W0, const P& Wl, const P& Wr, const P& Wm, const P& Wp, double kx, double ky,
-                            const Faces<double>& fb, P& W0b, P& Wlb, P& Wrb, P& Wmb, P& Wpb)
+CSH_HD void face_states_vjp_x(const P& W0, const P& Wl, const P& Wr, double kx, const Faces<double>& fb, P& W0b,
+                              P& Wlb, P& Wrb)
 {
     // ---- forward recompute ----
     const double ir = rcp(W0.r);
@@ -189,59 +255,14 @@ CSH_HD void face_states_vjp(const P& W0, const P& Wl, const P& Wr, const P& Wm, 
     const P dxm = limited_slope(W0, ex, dlx, drx);
     const double chix = 0.5 + kx * fmin(W0.u + ex.a, 0.0);
     const double clox = 0.5 - kx * fmax(W0.u - ex.a, 0.0);
-    P W0s{}, dyms{}, dym{}, dlys{}, drys{};
-    E ey{};
-    double chiy = 0, cloy = 0;
-    if constexpr (TWOD) {
-        W0s = swap(W0);
-        ey = eig_x(W0s, ir);
-        dlys = swap(sub(W0, Wm));
-        drys = swap(sub(Wp, W0));
-        dyms = limited_slope(W0s, ey, dlys, drys);
-        dym = swap(dyms);
-        chiy = 0.5 + ky * fmin(W0.v + ey.a, 0.0);
-        cloy = 0.5 - ky * fmax(W0.v - ey.a, 0.0);
-    }
     // ---- reverse ----
+    const P baseb = base_adjoint(fb, TWOD);
     double irb = 0.0;
-    E exb{0, 0, 0, 0, 0, 0}, eyb{0, 0, 0, 0, 0, 0};
-    P baseb = zero_p(), dxmb = zero_p(), dymb = zero_p();
-    // xhi = base + chix dxm ; xlo = base - clox dxm
-    acc(baseb, fb.xhi);
-    acc(baseb, fb.xlo);
+    E exb{0, 0, 0, 0, 0, 0};
+    P dxmb = zero_p();
     acc(dxmb, scale(chix, fb.xhi));
     acc(dxmb, scale(-clox, fb.xlo));
     const double chixb = dot(dxm, fb.xhi), cloxb = -dot(dxm, fb.xlo);
-    if constexpr (TWOD) {
-        acc(baseb, fb.yhi);
-        acc(baseb, fb.ylo);
-        acc(dymb, scale(chiy, fb.yhi));
-        acc(dymb, scale(-cloy, fb.ylo));
-        const double chiyb = dot(dym, fb.yhi), cloyb = -dot(dym, fb.ylo);
-        // chiy = 1/2 + ky min(v + ay, 0) ; cloy = 1/2 - ky max(v - ay, 0)
-        if (W0.v + ey.a < 0.0) {
-            W0b.v += ky * chiyb;
-            eyb.a += ky * chiyb;
-        }
-        if (W0.v - ey.a > 0.0) {
-            W0b.v -= ky * cloyb;
-            eyb.a += ky * cloyb;
-        }
-        // base -= ky swap(jac_x(W0s, ir, dyms))
-        P W0sb = zero_p(), dymsb = swapb(dymb);
-        jac_vjp(W0s, ir, dyms, scale(-ky, swapb(baseb)), W0sb, irb, dymsb);
-        // dyms = limited_slope(W0s, ey, dlys, drys)
-        P dlysb = zero_p(), drysb = zero_p();
-        limited_slope_vjp(W0s, ey, dlys, drys, dymsb, W0sb, eyb, dlysb, drysb);
-        eig_vjp(W0s, ir, ey, eyb, W0sb, irb);
-        acc(W0b, swapb(W0sb));
-        // dlys = swap(W0 - Wm), drys = swap(Wp - W0)
-        const P dlyb = swapb(dlysb), dryb = swapb(drysb);
-        acc(W0b, dlyb);
-        acc(Wmb, scale(-1.0, dlyb));
-        acc(Wpb, dryb);
-        acc(W0b, scale(-1.0, dryb));
-    }
     // chix = 1/2 + kx min(u + ax, 0) ; clox = 1/2 - kx max(u - ax, 0)
     if (W0.u + ex.a < 0.0) {
         W0b.u += kx * chixb;
@@ -251,7 +272,7 @@ CSH_HD void face_states_vjp(const P& W0, const P& Wl, const P& Wr, const P& Wm, 
         W0b.u -= kx * cloxb;
         exb.a += kx * cloxb;
     }
-    // base = W0 - kx jac_x(W0, ir, dxm) (- transverse term, done above)
+    // base = W0 - kx jac_x(W0, ir, dxm) (- the transverse term, in the y part)
     acc(W0b, baseb);
     jac_vjp(W0, ir, dxm, scale(-kx, baseb), W0b, irb, dxmb);
     P dlxb = zero_p(), drxb = zero_p();
@@ -264,6 +285,15 @@ CSH_HD void face_states_vjp(const P& W0, const P& Wl, const P& Wr, const P& Wm, 
     acc(W0b, scale(-1.0, drxb));
     // ir = 1 / W0.r
     W0b.r += -ir * ir * irb;
+}
+
+// reverse of face_states<double, TWOD>(W0, ir, Wl, Wr, Wm, Wp, kx, ky)
+template <bool TWOD>
+CSH_HD void face_states_vjp(const P& W0, const P& Wl, const P& Wr, const P& Wm, const P& Wp, double kx, double ky,
+                            const Faces<double>& fb, P& W0b, P& Wlb, P& Wrb, P& Wmb, P& Wpb)
+{
+    if constexpr (TWOD) face_states_vjp_y(W0, Wm, Wp, ky, fb, W0b, Wmb, Wpb);
+    face_states_vjp_x<TWOD>(W0, Wl, Wr, kx, fb, W0b, Wlb, Wrb);
 }
 
 // to_cons(w): mx = r u, my = r v, exx = pxx + mx u, exy = pxy + mx v, eyy = pyy + my v
@@ -464,6 +494,16 @@ CSH_HD void hll_cell(const AdjArgs& a, int i, int j)
     const size_t ne = (size_t)a.ex * a.ey;
     const size_t e = ext_index(a, i, j);
     const C z = zero_c();
+    // face-state adjoint slots of this cell that no face writes (the outer
+    // faces of the ring) are cleared here; every other slot is written by the
+    // one face that uses that state
+    const bool jin = !TWOD || (j >= 0 && j < a.ny), iin = i >= 0 && i < a.nx;
+    if (!(i <= a.nx - 1 && jin)) store_p(a.FSb, ne, XHI, e, zero_p());
+    if (!(i >= 0 && jin)) store_p(a.FSb, ne, XLO, e, zero_p());
+    if (TWOD) {
+        if (!(j <= a.ny - 1 && iin)) store_p(a.FSb, ne, YHI, e, zero_p());
+        if (!(j >= 0 && iin)) store_p(a.FSb, ne, YLO, e, zero_p());
+    }
     // x face i + 1/2 in an interior row: between extended cells (i, j) and (i + 1, j)
     if (i <= a.nx - 1 && (!TWOD || (j >= 0 && j < a.ny))) {
         const int jj = TWOD ? j : 0;
@@ -486,32 +526,58 @@ CSH_HD void hll_cell(const AdjArgs& a, int i, int j)
     }
 }
 
-template <bool TWOD>
-CSH_HD void cells_cell(const AdjArgs& a, int i, int j)
+CSH_HD Faces<double> load_face_adjoints(const AdjArgs& a, size_t ne, size_t e, bool twod)
 {
-    const double kx = a.dt / (2.0 * a.dx), ky = TWOD ? a.dt / (2.0 * a.dy) : 0.0;
-    const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
-    const P W0 = prim_at(a, i, j, TWOD);
-    const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
-    const P Wm = TWOD ? prim_at(a, i, j - 1, TWOD) : W0, Wp = TWOD ? prim_at(a, i, j + 1, TWOD) : W0;
     Faces<double> fb;
     fb.xhi = load_p(a.FSb, ne, XHI, e);
     fb.xlo = load_p(a.FSb, ne, XLO, e);
-    if (TWOD) {
+    if (twod) {
         fb.yhi = load_p(a.FSb, ne, YHI, e);
         fb.ylo = load_p(a.FSb, ne, YLO, e);
     } else {
         fb.yhi = fb.ylo = zero_p();
     }
-    P b0 = zero_p(), bl = zero_p(), br = zero_p(), bm = zero_p(), bp = zero_p();
-    face_states_vjp<TWOD>(W0, Wl, Wr, Wm, Wp, kx, ky, fb, b0, bl, br, bm, bp);
+    return fb;
+}
+
+// y part of the face-state adjoint of extended cell (i, j) (2-D): slots SELF
+// (its share), DOWN, UP
+CSH_HD void cells_cell_y(const AdjArgs& a, int i, int j)
+{
+    const double ky = a.dt / (2.0 * a.dy);
+    const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
+    const P W0 = prim_at(a, i, j, true);
+    const P Wm = prim_at(a, i, j - 1, true), Wp = prim_at(a, i, j + 1, true);
+    const Faces<double> fb = load_face_adjoints(a, ne, e, true);
+    P b0 = zero_p(), bm = zero_p(), bp = zero_p();
+    face_states_vjp_y(W0, Wm, Wp, ky, fb, b0, bm, bp);
+    store_p(a.Cs, ne, SELF, e, b0);
+    store_p(a.Cs, ne, DOWN, e, bm);
+    store_p(a.Cs, ne, UP, e, bp);
+}
+
+// x part: adds to SELF (2-D: after the y part), writes LEFT, RIGHT
+template <bool TWOD>
+CSH_HD void cells_cell_x(const AdjArgs& a, int i, int j)
+{
+    const double kx = a.dt / (2.0 * a.dx);
+    const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
+    const P W0 = prim_at(a, i, j, TWOD);
+    const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
+    const Faces<double> fb = load_face_adjoints(a, ne, e, TWOD);
+    P b0 = TWOD ? load_p(a.Cs, ne, SELF, e) : zero_p(), bl = zero_p(), br = zero_p();
+    face_states_vjp_x<TWOD>(W0, Wl, Wr, kx, fb, b0, bl, br);
     store_p(a.Cs, ne, SELF, e, b0);
     store_p(a.Cs, ne, LEFT, e, bl);
     store_p(a.Cs, ne, RIGHT, e, br);
-    if (TWOD) {
-        store_p(a.Cs, ne, DOWN, e, bm);
-        store_p(a.Cs, ne, UP, e, bp);
-    }
+}
+
+// both parts, in the order the GPU runs them (y kernel, then x kernel)
+template <bool TWOD>
+CSH_HD void cells_cell(const AdjArgs& a, int i, int j)
+{
+    if constexpr (TWOD) cells_cell_y(a, i, j);
+    cells_cell_x<TWOD>(a, i, j);
 }
 
 // positions p in [-2, n+1] (the ghost-padded range the stencil reads) with

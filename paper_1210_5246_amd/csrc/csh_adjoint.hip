@@ -14,7 +14,9 @@
 //              states, each written to its one slot in FSb
 //   3. cells:  per extended cell, the vjp of its face-state computation gives
 //              the adjoints of its five input primitive states -> slots
-//              C[self, left, right, down, up]
+//              C[self, left, right, down, up]; in two kernels, the y part
+//              (self, down, up) and then the x part (adds to self; left,
+//              right), which halves the live state of each
 //   4. gather: per interior cell, sum the slots that land on each padded
 //              position, fold the padded positions that the boundary mapping
 //              sends to this cell, chain through W(U) and add lam' itself.
@@ -41,15 +43,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a)
     const int j = TWOD ? (int)(t / a.ex) - 1 : 0;
     if (STAGE == 1) faces_cell<TWOD>(a, i, j);
     if (STAGE == 2) hll_cell<TWOD>(a, i, j);
-    if (STAGE == 3) cells_cell<TWOD>(a, i, j);
+    if constexpr (STAGE == 3 && TWOD) cells_cell_y(a, i, j);
+    if (STAGE == 5) cells_cell_x<TWOD>(a, i, j);
 }
 
-__global__ __launch_bounds__(256) void zero_kernel(double* p, int64_t n)
-{
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) p[k] = 0.0;
-}
-
-// W -> U (primitive to conserved) transposed: lam_W = (dU/dW)^T lam_U
 __global__ __launch_bounds__(256) void init_adjoint_kernel(const double* W, const double* lamU, double* lamW, int64_t n)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,18 +97,16 @@ int csh_adjoint_impl(csh_grid_view v, double dt, const void* U, const void* lam_
     a.FSb = ws + 24 * ne;
     a.Cs = ws + 48 * ne;
     const unsigned be = (unsigned)((ne + 255) / 256), bi = (unsigned)(((size_t)v.nx * v.ny + 255) / 256);
-    unsigned bz = (unsigned)((24 * ne + 255) / 256);
-    if (bz > 8192) bz = 8192;
-    zero_kernel<<<bz, 256, 0, s>>>(a.FSb, (int64_t)(24 * ne));
     if (twod) {
         adjoint_kernel<true, 1><<<be, 256, 0, s>>>(a);
         adjoint_kernel<true, 2><<<be, 256, 0, s>>>(a);
         adjoint_kernel<true, 3><<<be, 256, 0, s>>>(a);
+        adjoint_kernel<true, 5><<<be, 256, 0, s>>>(a);
         adjoint_kernel<true, 4><<<bi, 256, 0, s>>>(a);
     } else {
         adjoint_kernel<false, 1><<<be, 256, 0, s>>>(a);
         adjoint_kernel<false, 2><<<be, 256, 0, s>>>(a);
-        adjoint_kernel<false, 3><<<be, 256, 0, s>>>(a);
+        adjoint_kernel<false, 5><<<be, 256, 0, s>>>(a);
         adjoint_kernel<false, 4><<<bi, 256, 0, s>>>(a);
     }
     const hipError_t e = hipGetLastError();

@@ -3,6 +3,7 @@
 // the hand-written reverse pass against finite differences and the oracle's
 // dense Jacobian without a GPU.  Test infrastructure only.
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "csh_adjoint.h"
@@ -49,7 +50,8 @@ extern "C" int host_adjoint_step(int nx, int ny, int bcx, int bcy, double dx, do
 {
     AdjArgs a = make_args(nx, ny, bcx, bcy, dx, dy, dt, vc, rc, x0, y0, U);
     const size_t ne = (size_t)a.ex * a.ey;
-    std::vector<double> ws(78 * ne, 0.0);
+    // NaN-filled: every slot the reverse pass reads must have been written by it
+    std::vector<double> ws(78 * ne, std::numeric_limits<double>::quiet_NaN());
     a.FS = ws.data();
     a.FSb = ws.data() + 24 * ne;
     a.Cs = ws.data() + 48 * ne;
