@@ -158,7 +158,7 @@ CSH_HD Eig<T> eig_x(const Prim<T>& w, T ir)
     e.a = T(1.7320508075688772935) * e.c;  // sqrt(3) c
     e.h2c = T(0.5) * y;
     e.h2a = T(0.28867513459481288225) * y;  // 1 / (2 sqrt(3) c)
-    e.ip = rcp(w.pxx);
+    e.ip = y * y * ir;                      // 1 / Pxx = (rho / Pxx) / rho
     e.q = w.pxy * e.ip;
     return e;
 }
@@ -226,6 +226,64 @@ CSH_HD Prim<T> limited_slope(const Prim<T>& w, const Eig<T>& e, const Prim<T>& d
     return backproject(w, e, m);
 }
 
+// Half the MC limiter, mc(dl, dr) / 2, from order statistics: with
+// q = (dl + dr) / 4, lo = min(dl, dr), hi = max(dl, dr), A = min(lo, q) <= q <=
+// B = max(hi, q), and the result is the median of (A, 0, B): A when both
+// differences are positive, B when both are negative, 0 otherwise.  Equal to
+// the sign-tested form value for value (up to the sign of a zero); the factor
+// 2 it omits goes into the face-state coefficients.
+template <typename T>
+CSH_HD T mc_half(T dl, T dr)
+{
+    const T q = T(0.25) * (dl + dr);
+    const T A = fmin(fmin(dl, dr), q), B = fmax(fmax(dl, dr), q);
+    return fmax(A, fmin(B, T(0)));
+}
+
+// Half the characteristic MC-limited slope (eqs. (19)-(26)) in scaled form.
+// The limiter commutes with a positive factor common to its two arguments, so
+// each wave's amplitude is formed up to a per-cell positive scale and the
+// back-projection divides it out.  Amplitudes, x direction (q = Pxy / Pxx):
+//   u -+ a:  dPxx -+ rho a du                          (6 Pxx times l . d)
+//   u -+ c:  (dPxy - q dPxx) -+ rho c (q du - dv)      (2 Pxx times)
+//   u:       drho - rho / (3 Pxx) dPxx,  dPyy - 2 q dPxy + (4 q^2 - Pyy / Pxx) / 3 dPxx
+// and with S, D the sum and difference of the u -+ a pair, S', D' of the
+// u -+ c pair, the slope is
+//   (rho S / (6 Pxx) + m_rho, a D / (6 Pxx), a q D / (6 Pxx) + c D' / (2 Pxx),
+//    S / 2, (q S + S') / 2, (Pyy + 2 Pxy q) S / (6 Pxx) + q S' + m_Pyy).
+template <typename T>
+CSH_HD Prim<T> half_slope(const Prim<T>& w, const Eig<T>& e, const Prim<T>& dl, const Prim<T>& dr)
+{
+    const T ra = w.r * e.a, rc = w.r * e.c, q2 = e.q + e.q;
+    const T kr = w.r * e.ip * T(1.0 / 3.0);
+    const T k4 = (T(4) * e.q * e.q - w.pyy * e.ip) * T(1.0 / 3.0);
+    auto project = [&](const Prim<T>& d, T (&al)[6]) {
+        al[0] = d.pxx - ra * d.u;
+        al[5] = d.pxx + ra * d.u;
+        const T s = d.pxy - e.q * d.pxx, h = e.q * d.u - d.v;
+        al[1] = s + rc * h;
+        al[4] = s - rc * h;
+        al[2] = d.r - kr * d.pxx;
+        al[3] = d.pyy - q2 * d.pxy + k4 * d.pxx;
+    };
+    T l[6], r[6], m[6];
+    project(dl, l);
+    project(dr, r);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m[k] = mc_half(l[k], r[k]);
+    const T i6 = e.ip * T(1.0 / 6.0);
+    const T S = m[0] + m[5], D = m[5] - m[0], S2 = m[1] + m[4], D2 = m[4] - m[1];
+    const T bu = e.a * i6;
+    Prim<T> d;
+    d.r = (w.r * i6) * S + m[2];
+    d.u = bu * D;
+    d.v = (bu * e.q) * D + (e.c * e.ip * T(0.5)) * D2;
+    d.pxx = T(0.5) * S;
+    d.pxy = T(0.5) * (e.q * S + S2);
+    d.pyy = ((w.pyy + q2 * w.pxy) * i6) * S + e.q * S2 + m[3];
+    return d;
+}
+
 // A d with A the primitive x Jacobian (rows: u d_rho + rho d_u, u d_u + d_Pxx/rho,
 // u d_v + d_Pxy/rho, u d_Pxx + 3 Pxx d_u, u d_Pxy + 2 Pxy d_u + Pxx d_v,
 // u d_Pyy + Pyy d_u + 2 Pxy d_v).
@@ -269,23 +327,36 @@ CSH_HD Face<T> make_face_x(const Prim<T>& w)
     return f;
 }
 
-// HLL flux in x (Davis speed estimates), branch-free form.
+// F - s U for an x-face state, formed from the primitive state alone: with
+// s' = u - s and m = rho s', F - s U = s' U + N (N = (0, Pxx, Pxy, 2 Pxx u,
+// Pxy u + Pxx v, 2 Pxy v), the stress part of the flux) regroups to
+// (m, m u + Pxx, m v + Pxy, u X_mx + Pxx (s' + u), v X_mx + Pxy (s' + u),
+//  v (X_my + Pxy) + Pyy s').
+template <typename T>
+CSH_HD Cons<T> moving_flux_x(const Prim<T>& w, T s)
+{
+    const T sp = w.u - s;
+    const T m = w.r * sp;
+    const T xmx = m * w.u + w.pxx;
+    const T xmy = m * w.v + w.pxy;
+    const T g = sp + w.u;
+    return {m, xmx, xmy, w.u * xmx + w.pxx * g, w.v * xmx + w.pxy * g, w.v * (xmy + w.pxy) + w.pyy * sp};
+}
+
+// HLL flux in x (Davis speed estimates), branch-free form: with the outer
+// speeds clamped, S_L' = min(S_L, 0) and S_R' = max(S_R, 0), the three-case
+// flux is (S_R' F_L - S_L' F_R + S_L' S_R' (U_R - U_L)) / (S_R' - S_L'), which
+// is (S_R' X_L - S_L' X_R) / (S_R' - S_L') with X_K = F_K - S_K' U_K.
 template <typename T>
 CSH_HD Cons<T> hll_x(const Face<T>& L, const Face<T>& R)
 {
     const T sl = fmin(fmin(L.w.u - L.a, R.w.u - R.a), T(0));
     const T sr = fmax(fmax(L.w.u + L.a, R.w.u + R.a), T(0));
     const T inv = rcp(sr - sl);
-    const T a = sr * inv, b = sl * inv, c = sl * a;  // S_R', S_L', S_L' S_R' over S_R' - S_L'
-    const Cons<T> FL = flux_x(L.w, L.U), FR = flux_x(R.w, R.U);
-    Cons<T> F;
-    F.r = a * FL.r - b * FR.r + c * (R.U.r - L.U.r);
-    F.mx = a * FL.mx - b * FR.mx + c * (R.U.mx - L.U.mx);
-    F.my = a * FL.my - b * FR.my + c * (R.U.my - L.U.my);
-    F.exx = a * FL.exx - b * FR.exx + c * (R.U.exx - L.U.exx);
-    F.exy = a * FL.exy - b * FR.exy + c * (R.U.exy - L.U.exy);
-    F.eyy = a * FL.eyy - b * FR.eyy + c * (R.U.eyy - L.U.eyy);
-    return F;
+    const T a = sr * inv, b = sl * inv;
+    const Cons<T> XL = moving_flux_x(L.w, sl), XR = moving_flux_x(R.w, sr);
+    return {a * XL.r - b * XR.r,     a * XL.mx - b * XR.mx,   a * XL.my - b * XR.my,
+            a * XL.exx - b * XR.exx, a * XL.exy - b * XR.exy, a * XL.eyy - b * XR.eyy};
 }
 
 // HLLC flux in x for the moment equations: outer speeds as for HLL, one
@@ -353,25 +424,29 @@ template <typename T, bool TWOD>
 CSH_HD Faces<T> face_states(const Prim<T>& W0, T ir, const Prim<T>& Wl, const Prim<T>& Wr, const Prim<T>& Wm,
                             const Prim<T>& Wp, T kx, T ky)
 {
+    // with the half slopes h = dm / 2 every coefficient doubles:
+    // base = w - 2k A h, w_hi = base + (1 + 2k min(lamM, 0)) h, w_lo = base - (1 - 2k max(lam0, 0)) h
+    const T kx2 = kx + kx;
     const Eig<T> ex = eig_x(W0, ir);
-    const Prim<T> dxm = limited_slope(W0, ex, sub(W0, Wl), sub(Wr, W0));
-    Prim<T> base = axpy(-kx, jac_x(W0, ir, dxm), W0);
+    const Prim<T> hx = half_slope(W0, ex, sub(W0, Wl), sub(Wr, W0));
+    Prim<T> base = axpy(-kx2, jac_x(W0, ir, hx), W0);
     Faces<T> f;
-    const T chix = T(0.5) + kx * fmin(W0.u + ex.a, T(0));
-    const T clox = T(0.5) - kx * fmax(W0.u - ex.a, T(0));
+    const T chix = T(1) + kx2 * fmin(W0.u + ex.a, T(0));
+    const T clox = T(1) - kx2 * fmax(W0.u - ex.a, T(0));
     if constexpr (TWOD) {
+        const T ky2 = ky + ky;
         const Prim<T> W0s = swap(W0);
         const Eig<T> ey = eig_x(W0s, ir);
-        const Prim<T> dyms = limited_slope(W0s, ey, swap(sub(W0, Wm)), swap(sub(Wp, W0)));
-        base = axpy(-ky, swap(jac_x(W0s, ir, dyms)), base);
-        const Prim<T> dym = swap(dyms);
-        const T chiy = T(0.5) + ky * fmin(W0.v + ey.a, T(0));
-        const T cloy = T(0.5) - ky * fmax(W0.v - ey.a, T(0));
-        f.yhi = axpy(chiy, dym, base);
-        f.ylo = axpy(-cloy, dym, base);
+        const Prim<T> hys = half_slope(W0s, ey, swap(sub(W0, Wm)), swap(sub(Wp, W0)));
+        base = axpy(-ky2, swap(jac_x(W0s, ir, hys)), base);
+        const Prim<T> hy = swap(hys);
+        const T chiy = T(1) + ky2 * fmin(W0.v + ey.a, T(0));
+        const T cloy = T(1) - ky2 * fmax(W0.v - ey.a, T(0));
+        f.yhi = axpy(chiy, hy, base);
+        f.ylo = axpy(-cloy, hy, base);
     }
-    f.xhi = axpy(chix, dxm, base);
-    f.xlo = axpy(-clox, dxm, base);
+    f.xhi = axpy(chix, hx, base);
+    f.xlo = axpy(-clox, hx, base);
     return f;
 }
 
@@ -441,9 +516,10 @@ CSH_HD double signal_rate(const Prim<T>& w, double idx, double idy)
 template <typename T>
 CSH_HD bool physical(const Prim<T>& w)
 {
-    const bool pd = w.r > T(0) && w.pxx > T(0) && w.pyy > T(0) && w.pxx * w.pyy - w.pxy * w.pxy > T(0);
+    // every test evaluated (no short-circuit: no lane-divergent branches)
+    const bool pd = (w.r > T(0)) & (w.pxx > T(0)) & (w.pyy > T(0)) & (w.pxx * w.pyy - w.pxy * w.pxy > T(0));
     // a NaN or infinity in any component makes the sum NaN or infinite
-    return pd && isfinite(w.r + w.u + w.v + w.pxx + w.pxy + w.pyy);
+    return pd & isfinite(w.r + w.u + w.v + w.pxx + w.pxy + w.pyy);
 }
 
 // ---- wavefront primitives --------------------------------------------------------------------
@@ -478,6 +554,15 @@ __device__ __forceinline__ Cons<T> lane_shift(const Cons<T>& U)
 {
     return {lane_shift<D>(U.r), lane_shift<D>(U.mx), lane_shift<D>(U.my),
             lane_shift<D>(U.exx), lane_shift<D>(U.exy), lane_shift<D>(U.eyy)};
+}
+
+// Index of the calling wavefront in its workgroup, as a wave-uniform value
+// (threadIdx.x / 64 is the same on every lane of a wavefront, but the compiler
+// cannot see that; without the readfirstlane every branch on it is compiled
+// as lane-divergent control flow).
+__device__ __forceinline__ int wave_in_block()
+{
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
 
 // max over the wavefront

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
     }
 
     const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
+    const int wid = blockIdx.x * kWaves + wave_in_block();
     if (wid >= p.nstrips * p.nsegs) return;  // uniform per wavefront
     const int sx = wid % p.nstrips, sy = wid / p.nstrips;
     const int c = sx * kStrip - 2 + lane;  // column of this lane
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
         // one row: (Um, Wm) row r-1 (refilled with row r+2), (U0, W0, ir0) row r, Wp row r+1
         auto row = [&](int r, Cons<T>& Um, Prim<T>& Wm, T& irm, const Cons<T>& U0, const Prim<T>& W0, T ir0,
                        const Prim<T>& Wp) {
-            const Cons<T> Unext = (r + 2 <= y1 + 1) ? load_row(r + 2) : U0;
+            const Cons<T> Unext = load_row(min(r + 2, y1 + 1));  // past the window's end: a row already read
 
             // face states of (c, r): x neighbours from the adjacent lanes, y from the row window
             const Faces<T> fs =
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
                         out.store((unsigned)((r - 1) * p.nx + c), Un);
                         const Prim<T> wn = to_prim(Un);
                         smax = fmax(smax, signal_rate<T, true>(wn, idx, idy));
-                        bad = bad || !physical(wn);
+                        bad |= !physical(wn);
                     }
                 }
                 if (r < y1) {

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
         }
     }
     const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
+    const int wid = blockIdx.x * kWaves + wave_in_block();
     if (wid >= p.nstrips * p.nsegs) return;  // uniform per wavefront
     const int sx = wid % p.nstrips, sy = wid / p.nstrips;
     const int c = sx * kStrip - 2 + lane;
