@@ -252,10 +252,11 @@ CSH_HD T mc_half(T dl, T dr)
 //   (rho S / (6 Pxx) + m_rho, a D / (6 Pxx), a q D / (6 Pxx) + c D' / (2 Pxx),
 //    S / 2, (q S + S') / 2, (Pyy + 2 Pxy q) S / (6 Pxx) + q S' + m_Pyy).
 template <typename T>
-CSH_HD Prim<T> half_slope(const Prim<T>& w, const Eig<T>& e, const Prim<T>& dl, const Prim<T>& dr)
+CSH_HD Prim<T> half_slope(const Prim<T>& w, T ir, const Eig<T>& e, const Prim<T>& dl, const Prim<T>& dr)
 {
     const T ra = w.r * e.a, rc = w.r * e.c, q2 = e.q + e.q;
-    const T kr = w.r * e.ip * T(1.0 / 3.0);
+    const T rip = w.r * e.ip;  // rho / Pxx
+    const T kr = rip * T(1.0 / 3.0);
     const T k4 = (T(4) * e.q * e.q - w.pyy * e.ip) * T(1.0 / 3.0);
     auto project = [&](const Prim<T>& d, T (&al)[6]) {
         al[0] = d.pxx - ra * d.u;
@@ -275,9 +276,9 @@ CSH_HD Prim<T> half_slope(const Prim<T>& w, const Eig<T>& e, const Prim<T>& dl, 
     const T S = m[0] + m[5], D = m[5] - m[0], S2 = m[1] + m[4], D2 = m[4] - m[1];
     const T bu = e.a * i6;
     Prim<T> d;
-    d.r = (w.r * i6) * S + m[2];
+    d.r = (rip * T(1.0 / 6.0)) * S + m[2];
     d.u = bu * D;
-    d.v = (bu * e.q) * D + (e.c * e.ip * T(0.5)) * D2;
+    d.v = (bu * e.q) * D + (e.h2c * ir) * D2;  // c / (2 Pxx) = 1 / (2 c rho)
     d.pxx = T(0.5) * S;
     d.pxy = T(0.5) * (e.q * S + S2);
     d.pyy = ((w.pyy + q2 * w.pxy) * i6) * S + e.q * S2 + m[3];
@@ -428,7 +429,7 @@ CSH_HD Faces<T> face_states(const Prim<T>& W0, T ir, const Prim<T>& Wl, const Pr
     // base = w - 2k A h, w_hi = base + (1 + 2k min(lamM, 0)) h, w_lo = base - (1 - 2k max(lam0, 0)) h
     const T kx2 = kx + kx;
     const Eig<T> ex = eig_x(W0, ir);
-    const Prim<T> hx = half_slope(W0, ex, sub(W0, Wl), sub(Wr, W0));
+    const Prim<T> hx = half_slope(W0, ir, ex, sub(W0, Wl), sub(Wr, W0));
     Prim<T> base = axpy(-kx2, jac_x(W0, ir, hx), W0);
     Faces<T> f;
     const T chix = T(1) + kx2 * fmin(W0.u + ex.a, T(0));
@@ -437,7 +438,7 @@ CSH_HD Faces<T> face_states(const Prim<T>& W0, T ir, const Prim<T>& Wl, const Pr
         const T ky2 = ky + ky;
         const Prim<T> W0s = swap(W0);
         const Eig<T> ey = eig_x(W0s, ir);
-        const Prim<T> hys = half_slope(W0s, ey, swap(sub(W0, Wm)), swap(sub(Wp, W0)));
+        const Prim<T> hys = half_slope(W0s, ir, ey, swap(sub(W0, Wm)), swap(sub(Wp, W0)));
         base = axpy(-ky2, swap(jac_x(W0s, ir, hys)), base);
         const Prim<T> hy = swap(hys);
         const T chiy = T(1) + ky2 * fmin(W0.v + ey.a, T(0));
@@ -486,15 +487,17 @@ __device__ __forceinline__ void kick(Cons<T>& U, const P& p, double dt, int i, i
     if (p.vc2 == 0.0) return;
     const double x = p.x0 + (i + 0.5) * p.dx;
     const double y = twod ? p.y0 + (j + 0.5) * p.dy : 0.0;
-    const double f = -p.vc2 * rcp(x * x + y * y + p.rc2);
-    const T ax = T(f * x), ay = T(f * y);
-    const T h = T(dt);
-    const T mx = U.mx, my = U.my;
-    U.mx = mx + h * U.r * ax;
-    U.my = my + h * U.r * ay;
-    U.exx = U.exx + h * ax * (T(2) * mx + h * U.r * ax);
-    U.exy = U.exy + h * (ax * my + mx * ay + h * U.r * ax * ay);
-    U.eyy = U.eyy + h * ay * (T(2) * my + h * U.r * ay);
+    // velocity increment g = dt a, a = -vc2 (x, y) / (x^2 + y^2 + rc^2)
+    const double f = (-p.vc2 * dt) * rcp(x * x + y * y + p.rc2);
+    const T gx = T(f * x), gy = T(f * y);
+    // m' = m + rho g; E' = E + g_i m_j + m_i g_j + rho g_i g_j, i.e.
+    // E'_xx = E_xx + g_x (m_x + m'_x), E'_xy = E_xy + g_x m_y + g_y m'_x
+    const T mx = U.mx + U.r * gx, my = U.my + U.r * gy;
+    U.exx = U.exx + gx * (U.mx + mx);
+    U.exy = U.exy + gx * U.my + gy * mx;
+    U.eyy = U.eyy + gy * (U.my + my);
+    U.mx = mx;
+    U.my = my;
 }
 
 // CFL rate of a cell (the timestep is C / max over cells of this):
@@ -509,6 +512,21 @@ CSH_HD double signal_rate(const Prim<T>& w, double idx, double idy)
         const double ty = 3.0 * double(w.pyy) * ir;
         s += (fabs(double(w.v)) + ty * rsqrt(ty)) * idy;
     }
+    return s;
+}
+
+// CFL rate of a new 2-D state together with the test of physical() (rho > 0,
+// positive-definite stress, everything finite), sharing the work: a NaN or an
+// infinity in u, v, Pxx or Pyy makes the rate NaN or infinite, one in Pxy
+// fails det > 0, one in rho fails rho > 0 or makes rate + rho infinite.
+template <typename T>
+CSH_HD double checked_rate(const Cons<T>& U, double idx, double idy, bool& bad)
+{
+    const Prim<T> w = to_prim(U);
+    const double s = signal_rate<T, true>(w, idx, idy);
+    const bool ok = (w.r > T(0)) & (w.pxx > T(0)) & (w.pyy > T(0)) & (w.pxx * w.pyy - w.pxy * w.pxy > T(0)) &
+                    isfinite(s + double(w.r));
+    bad |= !ok;
     return s;
 }
 

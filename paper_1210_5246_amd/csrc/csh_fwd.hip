@@ -120,9 +120,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
                     kick(Un, p, dt, c, r - 1, true);
                     if (own) {
                         out.store((unsigned)((r - 1) * p.nx + c), Un);
-                        const Prim<T> wn = to_prim(Un);
-                        smax = fmax(smax, signal_rate<T, true>(wn, idx, idy));
-                        bad |= !physical(wn);
+                        smax = fmax(smax, checked_rate(Un, idx, idy, bad));
                     }
                 }
                 if (r < y1) {
