@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
     const double dt = step_dt(p, &t_now);
     if (blockIdx.x == 0 && threadIdx.x == 0) p.slots[p.s_out].s_bits = 0ull;
     const int lane = threadIdx.x & 63;
-    const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long wid = (long)blockIdx.x * 4 + wave_in_block();
     const int ey = p.n[1] + 2;
     if (wid >= (long)q.nsegs * q.nstrips * ey) return;  // uniform per wavefront
     const int jj = (int)(wid % ey), sx = (int)((wid / ey) % q.nstrips), sz = (int)(wid / ((long)ey * q.nstrips));
@@ -114,8 +114,9 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
     const int gjm = map_index(j - 1, ny, p.bc[1]), gj0 = map_index(j, ny, p.bc[1]), gjp = map_index(j + 1, ny, p.bc[1]);
     const size_t plane = (size_t)nx * ny, ncell = plane * nz;
     const size_t fplane = (size_t)nx * ey, nf = fplane * nz;
-    const double kx = 0.5 * dt / p.h[0], ky = 0.5 * dt / p.h[1], kz = 0.5 * dt / p.h[2];
-    const double cx = dt / p.h[0], cz = dt / p.h[2];
+    // with half slopes the tracing coefficients are dt/h (twice dt/2h)
+    const double kx2 = dt / p.h[0], ky2 = dt / p.h[1], kz2 = dt / p.h[2];
+    const double cx = kx2, cz = kz2;
     const int z0 = sz * q.tz, z1 = min(z0 + q.tz, nz);
 
     auto cell = [&](int gj, int r) -> size_t {
@@ -139,38 +140,41 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
         // the next step's loads first
         const V10 Cz_n = ld(gj0, r + 2), Cym_n = ld(gjm, r + 1), Cyp_n = ld(gjp, r + 1);
         const double ir = rcp(W0.v[0]);
-        const double a = 1.7320508075688772935 * sqrt(ir);
-        auto coef = [&](int k, double kf, double& chi, double& clo) {
-            const double ak = a * sqrt(W0.v[P(k, k)]), uk = W0.v[1 + k];
-            chi = 0.5 + kf * fmin(uk + ak, 0.0);
-            clo = 0.5 - kf * fmax(uk - ak, 0.0);
+        double a3[3];  // fast speeds sqrt(3 P_kk / rho)
+        auto coef = [&](int k, double k2, double& chi, double& clo) {
+            const double ak = a3[k], uk = W0.v[1 + k];
+            chi = 1.0 + k2 * fmin(uk + ak, 0.0);
+            clo = 1.0 - k2 * fmax(uk - ak, 0.0);
         };
-        V10 base = W0, dz, dy, dx;
+        V10 base = W0, dz, dy, dx;  // half slopes
         {
             const Eig<0> e = eig<0>(W0, ir);
-            dx = limited_slope<0>(W0, e, shift<-1>(W0), shift<+1>(W0));
+            a3[0] = e.a;
+            dx = half_slope<0>(W0, ir, e, shift<-1>(W0), shift<+1>(W0));
             const V10 Ad = jac<0>(W0, ir, dx);
 #pragma unroll
-            for (int m = 0; m < NV; ++m) base.v[m] -= kx * Ad.v[m];
+            for (int m = 0; m < NV; ++m) base.v[m] -= kx2 * Ad.v[m];
         }
         {
             const Eig<1> e = eig<1>(W0, ir);
-            dy = limited_slope<1>(W0, e, prim(Cym), prim(Cyp));
+            a3[1] = e.a;
+            dy = half_slope<1>(W0, ir, e, prim(Cym), prim(Cyp));
             const V10 Ad = jac<1>(W0, ir, dy);
 #pragma unroll
-            for (int m = 0; m < NV; ++m) base.v[m] -= ky * Ad.v[m];
+            for (int m = 0; m < NV; ++m) base.v[m] -= ky2 * Ad.v[m];
         }
         const V10 Wp = prim(Cz);
         {
             const Eig<2> e = eig<2>(W0, ir);
-            dz = limited_slope<2>(W0, e, Wm, Wp);
+            a3[2] = e.a;
+            dz = half_slope<2>(W0, ir, e, Wm, Wp);
             const V10 Ad = jac<2>(W0, ir, dz);
 #pragma unroll
-            for (int m = 0; m < NV; ++m) base.v[m] -= kz * Ad.v[m];
+            for (int m = 0; m < NV; ++m) base.v[m] -= kz2 * Ad.v[m];
         }
         double ch, cl;
         if (r >= z0 && r < z1 && own) {  // the y-face states of (c, j, r)
-            coef(1, ky, ch, cl);
+            coef(1, ky2, ch, cl);
             const size_t f = ((size_t)r * ey + jj) * nx + c;
 #pragma unroll
             for (int m = 0; m < NV; ++m) {
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
                 q.FY[(NV + m) * nf + f] = base.v[m] + ch * dy.v[m];
             }
         }
-        coef(2, kz, ch, cl);
+        coef(2, kz2, ch, cl);
         V10 zhi;
         if (r >= z0) {
             V10 zlo;
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
         for (int m = 0; m < NV; ++m) zhi.v[m] = base.v[m] + ch * dz.v[m];
         zhi_prev = zhi;
         if (r >= z0 && r < z1) {
-            coef(0, kx, ch, cl);
+            coef(0, kx2, ch, cl);
             V10 xlo, xhi;
 #pragma unroll
             for (int m = 0; m < NV; ++m) {
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(256) void yflux3_kernel(MArgs q, int ty)
             }
             const V10 wn = to_prim(Un, rcp(Un.v[0]));
             smax = fmax(smax, signal_rate(wn, ih));
-            bad = bad || !physical(wn);
+            bad |= !physical(wn);
             Gm = Gp;
         }
     }
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(256) void maxspeed3_kernel(const double* __restrict
         const V10 u = load(U, (size_t)n, (size_t)c);
         const V10 w = to_prim(u, rcp(u.v[0]));
         s = fmax(s, signal_rate(w, ih));
-        bad = bad || !physical(w);
+        bad |= !physical(w);
     }
     s = wave_max(s);
     if ((threadIdx.x & 63) == 0) atomic_max_pos(&slot->s_bits, s);

@@ -12,7 +12,9 @@
 //   u + c (t1), u + c (t2), u + a,    a = sqrt(3 P_nn / rho), c = sqrt(P_nn / rho),
 // projected and back-projected in closed form (q_t = P_nt / P_nn); the
 // tracing uses the collapsed form of eqs. (27)-(32) with the HLL terms, which
-// needs only the extreme speeds u -+ a.
+// needs only the extreme speeds u -+ a.  As in two dimensions the kernels carry
+// half slopes (the face-state coefficients take the factor 2) and form each
+// wave's amplitude up to a positive per-cell scale.
 #pragma once
 
 #include "csh_device.h"
@@ -64,23 +66,6 @@ CSH_HD V10 to_cons(const V10& w)
     return U;
 }
 
-// flux along N: rho u_n, rho u_i u_n + P_in, E_ij u_n + P_ni u_j + P_nj u_i
-template <int N>
-CSH_HD V10 flux(const V10& w, const V10& U)
-{
-    V10 F;
-    const double un = w.v[1 + N];
-    F.v[0] = U.v[1 + N];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) F.v[1 + i] = U.v[1 + i] * un + w.v[P(i, N)];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j)
-            F.v[P(i, j)] = U.v[P(i, j)] * un + w.v[P(N, i)] * w.v[1 + j] + w.v[P(N, j)] * w.v[1 + i];
-    return F;
-}
-
 // A d with A the primitive Jacobian along N
 template <int N>
 CSH_HD V10 jac(const V10& w, double ir, const V10& d)
@@ -101,7 +86,7 @@ CSH_HD V10 jac(const V10& w, double ir, const V10& d)
 
 template <int N>
 struct Eig {
-    double a, c, h2a, h2c, ip, q1, q2;
+    double a, c, h2c, ip, q1, q2;  // a = sqrt(3 Pnn / rho), c = sqrt(Pnn / rho), h2c = 1/(2c), ip = 1/Pnn
 };
 
 template <int N>
@@ -115,93 +100,127 @@ CSH_HD Eig<N> eig(const V10& w, double ir)
     e.c = t * y;
     e.a = 1.7320508075688772935 * e.c;
     e.h2c = 0.5 * y;
-    e.h2a = 0.28867513459481288225 * y;
-    e.ip = rcp(pnn);
+    e.ip = y * y * ir;          // (rho / Pnn) / rho
     e.q1 = w.v[P(N, t1)] * e.ip;
     e.q2 = w.v[P(N, t2)] * e.ip;
     return e;
 }
 
-// amplitudes on the ten waves, in the order of the header comment
-template <int N>
-CSH_HD V10 project(const V10& w, const Eig<N>& e, const V10& d)
+// Half the MC limiter, mc(dl, dr) / 2, from order statistics: with
+// q = (dl + dr) / 4 the result is the median of (min(dl, dr, q), 0,
+// max(dl, dr, q)).
+CSH_HD double mc_half(double dl, double dr)
 {
-    constexpr int t1 = Axes<N>::t1, t2 = Axes<N>::t2;
-    const double dnn = d.v[P(N, N)];
-    const double f1 = dnn * e.ip * (1.0 / 6.0), f2 = d.v[1 + N] * e.h2a;
-    const double hip = 0.5 * e.ip;
-    const double s1 = (d.v[P(N, t1)] - e.q1 * dnn) * hip, h1 = (e.q1 * d.v[1 + N] - d.v[1 + t1]) * e.h2c;
-    const double s2 = (d.v[P(N, t2)] - e.q2 * dnn) * hip, h2 = (e.q2 * d.v[1 + N] - d.v[1 + t2]) * e.h2c;
-    const double third = dnn * (1.0 / 3.0);
-    V10 al;
-    al.v[0] = f1 - f2;
-    al.v[9] = f1 + f2;
-    al.v[1] = h1 + s1;
-    al.v[7] = s1 - h1;
-    al.v[2] = h2 + s2;
-    al.v[8] = s2 - h2;
-    al.v[3] = d.v[0] - w.v[0] * e.ip * third;
-    al.v[4] = d.v[P(t1, t1)] - 2.0 * e.q1 * d.v[P(N, t1)] + (4.0 * e.q1 * e.q1 - w.v[P(t1, t1)] * e.ip) * third;
-    al.v[5] = d.v[P(t1, t2)] - e.q2 * d.v[P(N, t1)] - e.q1 * d.v[P(N, t2)] +
-              (4.0 * e.q1 * e.q2 - w.v[P(t1, t2)] * e.ip) * third;
-    al.v[6] = d.v[P(t2, t2)] - 2.0 * e.q2 * d.v[P(N, t2)] + (4.0 * e.q2 * e.q2 - w.v[P(t2, t2)] * e.ip) * third;
-    return al;
+    const double q = 0.25 * (dl + dr);
+    const double A = fmin(fmin(dl, dr), q), B = fmax(fmax(dl, dr), q);
+    return fmax(A, fmin(B, 0.0));
 }
 
+// Half the characteristic MC-limited slope along N (eqs. (19)-(26)).  The
+// limiter commutes with a positive factor common to its two arguments, so the
+// amplitudes are formed up to per-cell positive scales:
+//   u -+ a:          dPnn -+ rho a du_n                          (6 Pnn times l . d)
+//   u -+ c (t):      (dPnt - q_t dPnn) -+ rho c (q_t du_n - du_t)  (2 Pnn times)
+//   u (4 waves):     drho - rho dPnn / (3 Pnn) and the three transverse-stress
+//                    combinations, unscaled;
+// the back-projection divides the scales out.
 template <int N>
-CSH_HD V10 backproject(const V10& w, const Eig<N>& e, const V10& al)
+CSH_HD V10 half_slope(const V10& w, double ir, const Eig<N>& e, const V10& wm, const V10& wp)
 {
     constexpr int t1 = Axes<N>::t1, t2 = Axes<N>::t2;
-    const double S = al.v[0] + al.v[9], D = al.v[9] - al.v[0];
-    const double S1 = al.v[1] + al.v[7], D1 = al.v[7] - al.v[1];
-    const double S2 = al.v[2] + al.v[8], D2 = al.v[8] - al.v[2];
-    const double pnn = w.v[P(N, N)], pn1 = w.v[P(N, t1)], pn2 = w.v[P(N, t2)];
+    constexpr int nn = P(N, N), n1 = P(N, t1), n2 = P(N, t2), s11 = P(t1, t1), s12 = P(t1, t2), s22 = P(t2, t2);
+    const double rho = w.v[0];
+    const double ra = rho * e.a, rc = rho * e.c, rip = rho * e.ip;
+    const double kr = rip * (1.0 / 3.0);
+    const double k11 = (4.0 * e.q1 * e.q1 - w.v[s11] * e.ip) * (1.0 / 3.0);
+    const double k12 = (4.0 * e.q1 * e.q2 - w.v[s12] * e.ip) * (1.0 / 3.0);
+    const double k22 = (4.0 * e.q2 * e.q2 - w.v[s22] * e.ip) * (1.0 / 3.0);
+    const double q1x2 = e.q1 + e.q1, q2x2 = e.q2 + e.q2;
+    auto project = [&](const V10& d, double (&al)[NV]) {
+        const double dnn = d.v[nn], dun = d.v[1 + N];
+        al[0] = dnn - ra * dun;
+        al[9] = dnn + ra * dun;
+        const double s1 = d.v[n1] - e.q1 * dnn, h1 = e.q1 * dun - d.v[1 + t1];
+        const double s2 = d.v[n2] - e.q2 * dnn, h2 = e.q2 * dun - d.v[1 + t2];
+        al[1] = s1 + rc * h1;
+        al[7] = s1 - rc * h1;
+        al[2] = s2 + rc * h2;
+        al[8] = s2 - rc * h2;
+        al[3] = d.v[0] - kr * dnn;
+        al[4] = d.v[s11] - q1x2 * d.v[n1] + k11 * dnn;
+        al[5] = d.v[s12] - e.q2 * d.v[n1] - e.q1 * d.v[n2] + k12 * dnn;
+        al[6] = d.v[s22] - q2x2 * d.v[n2] + k22 * dnn;
+    };
+    double l[NV], r[NV], m[NV];
+    {
+        V10 dl, dr;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            dl.v[k] = w.v[k] - wm.v[k];
+            dr.v[k] = wp.v[k] - w.v[k];
+        }
+        project(dl, l);
+        project(dr, r);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) m[k] = mc_half(l[k], r[k]);
+    const double S = m[0] + m[9], D = m[9] - m[0];
+    const double S1 = m[1] + m[7], D1 = m[7] - m[1];
+    const double S2 = m[2] + m[8], D2 = m[8] - m[2];
+    const double i6 = e.ip * (1.0 / 6.0), bu = e.a * i6, bc = e.h2c * ir;  // a / (6 Pnn), c / (2 Pnn)
+    const double pn1 = w.v[n1], pn2 = w.v[n2];
     V10 d;
-    d.v[0] = w.v[0] * S + al.v[3];
-    d.v[1 + N] = e.a * D;
-    d.v[1 + t1] = e.a * e.q1 * D + e.c * D1;
-    d.v[1 + t2] = e.a * e.q2 * D + e.c * D2;
-    d.v[P(N, N)] = 3.0 * pnn * S;
-    d.v[P(N, t1)] = 3.0 * pn1 * S + pnn * S1;
-    d.v[P(N, t2)] = 3.0 * pn2 * S + pnn * S2;
-    d.v[P(t1, t1)] = (w.v[P(t1, t1)] + 2.0 * pn1 * e.q1) * S + 2.0 * pn1 * S1 + al.v[4];
-    d.v[P(t1, t2)] = (w.v[P(t1, t2)] + pn1 * e.q2 + pn2 * e.q1) * S + pn2 * S1 + pn1 * S2 + al.v[5];
-    d.v[P(t2, t2)] = (w.v[P(t2, t2)] + 2.0 * pn2 * e.q2) * S + 2.0 * pn2 * S2 + al.v[6];
+    d.v[0] = (rip * (1.0 / 6.0)) * S + m[3];
+    d.v[1 + N] = bu * D;
+    d.v[1 + t1] = (bu * e.q1) * D + bc * D1;
+    d.v[1 + t2] = (bu * e.q2) * D + bc * D2;
+    d.v[nn] = 0.5 * S;
+    d.v[n1] = 0.5 * (e.q1 * S + S1);
+    d.v[n2] = 0.5 * (e.q2 * S + S2);
+    d.v[s11] = ((w.v[s11] + q1x2 * pn1) * i6) * S + e.q1 * S1 + m[4];
+    d.v[s12] = ((w.v[s12] + pn1 * e.q2 + pn2 * e.q1) * i6) * S + 0.5 * (e.q2 * S1 + e.q1 * S2) + m[5];
+    d.v[s22] = ((w.v[s22] + q2x2 * pn2) * i6) * S + e.q2 * S2 + m[6];
     return d;
 }
 
-// characteristic MC-limited slope along N (eqs. (19)-(26))
+// F - s U along N, formed from the primitive state: with s' = u_n - s and
+// m = rho s', X_rho = m, X_i = m u_i + P_in, X_ij = u_j X_i + s' P_ij + P_nj u_i,
+// which for i = n is u_j X_n + P_nj (s' + u_n).
 template <int N>
-CSH_HD V10 limited_slope(const V10& w, const Eig<N>& e, const V10& wm, const V10& wp)
+CSH_HD V10 moving_flux(const V10& w, double s)
 {
-    V10 dl, dr;
+    const double un = w.v[1 + N], sp = un - s, m = w.v[0] * sp, g = sp + un;
+    V10 X;
+    X.v[0] = m;
 #pragma unroll
-    for (int m = 0; m < NV; ++m) {
-        dl.v[m] = w.v[m] - wm.v[m];
-        dr.v[m] = wp.v[m] - w.v[m];
-    }
-    const V10 l = project<N>(w, e, dl), r = project<N>(w, e, dr);
-    V10 am;
+    for (int i = 0; i < 3; ++i) X.v[1 + i] = m * w.v[1 + i] + w.v[P(i, N)];
 #pragma unroll
-    for (int m = 0; m < NV; ++m) am.v[m] = mc(l.v[m], r.v[m]);
-    return backproject<N>(w, e, am);
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            if (i == N) X.v[P(i, j)] = w.v[1 + j] * X.v[1 + N] + w.v[P(N, j)] * g;
+            else if (j == N) X.v[P(i, j)] = w.v[1 + i] * X.v[1 + N] + w.v[P(N, i)] * g;
+            else X.v[P(i, j)] = w.v[1 + j] * X.v[1 + i] + sp * w.v[P(i, j)] + w.v[P(N, j)] * w.v[1 + i];
+        }
+    return X;
 }
 
-// HLL flux along N between face states (Davis speeds)
+// HLL flux along N between face states (Davis speeds); with the clamped
+// outer speeds S_L' = min(S_L, 0), S_R' = max(S_R, 0) it is
+// (S_R' X_L - S_L' X_R) / (S_R' - S_L'), X_K = F_K - S_K' U_K.
 template <int N>
 CSH_HD V10 hll(const V10& wl, const V10& wr)
 {
-    const V10 Ul = to_cons(wl), Ur = to_cons(wr);
-    const V10 Fl = flux<N>(wl, Ul), Fr = flux<N>(wr, Ur);
     const double tl = 3.0 * wl.v[P(N, N)], tr = 3.0 * wr.v[P(N, N)];
     const double al = tl * rsqrt(tl * wl.v[0]), ar = tr * rsqrt(tr * wr.v[0]);
     const double sl = fmin(fmin(wl.v[1 + N] - al, wr.v[1 + N] - ar), 0.0);
     const double sr = fmax(fmax(wl.v[1 + N] + al, wr.v[1 + N] + ar), 0.0);
     const double inv = rcp(sr - sl);
-    const double a = sr * inv, b = sl * inv, c = sl * a;
+    const double a = sr * inv, b = sl * inv;
+    const V10 XL = moving_flux<N>(wl, sl), XR = moving_flux<N>(wr, sr);
     V10 F;
 #pragma unroll
-    for (int m = 0; m < NV; ++m) F.v[m] = a * Fl.v[m] - b * Fr.v[m] + c * (Ur.v[m] - Ul.v[m]);
+    for (int m = 0; m < NV; ++m) F.v[m] = a * XL.v[m] - b * XR.v[m];
     return F;
 }
 
@@ -226,7 +245,7 @@ CSH_HD bool physical(const V10& w)
     double sum = 0.0;
 #pragma unroll
     for (int m = 0; m < NV; ++m) sum += w.v[m];
-    return w.v[0] > 0.0 && pxx > 0.0 && m2 > 0.0 && det > 0.0 && isfinite(sum);
+    return (w.v[0] > 0.0) & (pxx > 0.0) & (m2 > 0.0) & (det > 0.0) & isfinite(sum);
 }
 
 }  // namespace d3

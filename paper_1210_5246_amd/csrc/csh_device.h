@@ -453,28 +453,26 @@ CSH_HD Faces<T> face_states(const Prim<T>& W0, T ir, const Prim<T>& Wl, const Pr
 
 // ---- Kurganov-Tadmor central scheme (Sec. 3.2) ------------------------------------------------
 
-// component-wise MC-limited slope of the primitive variables
+// half the component-wise MC-limited slope of the primitive variables
 template <typename T>
-CSH_HD Prim<T> mc_slope(const Prim<T>& wm, const Prim<T>& w0, const Prim<T>& wp)
+CSH_HD Prim<T> mc_half_slope(const Prim<T>& wm, const Prim<T>& w0, const Prim<T>& wp)
 {
-    return {mc(w0.r - wm.r, wp.r - w0.r),       mc(w0.u - wm.u, wp.u - w0.u),
-            mc(w0.v - wm.v, wp.v - w0.v),       mc(w0.pxx - wm.pxx, wp.pxx - w0.pxx),
-            mc(w0.pxy - wm.pxy, wp.pxy - w0.pxy), mc(w0.pyy - wm.pyy, wp.pyy - w0.pyy)};
+    return {mc_half(w0.r - wm.r, wp.r - w0.r),       mc_half(w0.u - wm.u, wp.u - w0.u),
+            mc_half(w0.v - wm.v, wp.v - w0.v),       mc_half(w0.pxx - wm.pxx, wp.pxx - w0.pxx),
+            mc_half(w0.pxy - wm.pxy, wp.pxy - w0.pxy), mc_half(w0.pyy - wm.pyy, wp.pyy - w0.pyy)};
 }
 
-// x flux of eq. (6), H = (F(u-) + F(u+))/2 - a/2 (u+ - u-), from the face states
-// u- = wl, u+ = wr, a = max over the two of |u| + sqrt(3 Pxx / rho) (eqs. (7)-(8))
+// Twice the x flux of eq. (6), 2H = F(u-) + F(u+) - a (u+ - u-), from the face
+// states u- = wl, u+ = wr, a = max over the two of |u| + sqrt(3 Pxx / rho)
+// (eqs. (7)-(8)); as (F - s U) at s = -a on the left plus s = a on the right,
+// formed from the primitive states (moving_flux_x).
 template <typename T>
-CSH_HD Cons<T> kt_flux_x(const Prim<T>& wl, const Prim<T>& wr)
+CSH_HD Cons<T> kt_flux2_x(const Prim<T>& wl, const Prim<T>& wr)
 {
-    const Cons<T> UL = to_cons(wl), UR = to_cons(wr);
-    const Cons<T> FL = flux_x(wl, UL), FR = flux_x(wr, UR);
     const T tl = T(3) * wl.pxx, tr = T(3) * wr.pxx;
     const T a = fmax(fabs(wl.u) + tl * rsqrt(tl * wl.r), fabs(wr.u) + tr * rsqrt(tr * wr.r));
-    const T h = T(0.5) * a;
-    return {T(0.5) * (FL.r + FR.r) - h * (UR.r - UL.r),       T(0.5) * (FL.mx + FR.mx) - h * (UR.mx - UL.mx),
-            T(0.5) * (FL.my + FR.my) - h * (UR.my - UL.my),    T(0.5) * (FL.exx + FR.exx) - h * (UR.exx - UL.exx),
-            T(0.5) * (FL.exy + FR.exy) - h * (UR.exy - UL.exy), T(0.5) * (FL.eyy + FR.eyy) - h * (UR.eyy - UL.eyy)};
+    const Cons<T> XL = moving_flux_x(wl, -a), XR = moving_flux_x(wr, a);
+    return {XL.r + XR.r, XL.mx + XR.mx, XL.my + XR.my, XL.exx + XR.exx, XL.exy + XR.exy, XL.eyy + XR.eyy};
 }
 
 // External flat-rotation-curve potential (Sec. 3.3, last paragraph): exact

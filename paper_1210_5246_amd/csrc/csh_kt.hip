@@ -7,7 +7,8 @@
 // stage is one launch with the work decomposition of the characteristic sweep
 // (a wavefront per 60-column strip, marching up a row segment, neighbours by
 // DPP lane shifts); the first stage records the step's timestep in its input
-// slot for the second.
+// slot for the second.  The kernels carry half slopes (face states w -+ h)
+// and twice the flux (the update coefficients take the 1/2).
 #include "csh_device.h"
 #include "csh_internal.h"
 
@@ -29,9 +30,9 @@ __device__ __forceinline__ double kt_dt(const StepArgs<T>& p, double* t_now)
 }
 
 template <typename T>
-__device__ __forceinline__ Prim<T> half_step(const Prim<T>& w, T s, const Prim<T>& d)
+__device__ __forceinline__ Prim<T> plus(const Prim<T>& w, const Prim<T>& d)
 {
-    return axpy(s, d, w);
+    return {w.r + d.r, w.u + d.u, w.v + d.v, w.pxx + d.pxx, w.pxy + d.pxy, w.pyy + d.pyy};
 }
 
 template <typename T, bool TWOD, bool FINAL>
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
     const bool own = lane >= 2 && lane < 2 + kStrip && c < p.nx;
     const size_t plane = (size_t)p.nx * p.ny;
     const double h = FINAL ? dt : 0.5 * dt;  // stage length
-    const T cx = T(h / p.dx);
+    const T cx = T(0.5 * h / p.dx);  // the fluxes below are 2H
     const double idx = 1.0 / p.dx, idy = TWOD ? 1.0 / p.dy : 0.0;
     const Planes<T> in(p.U, plane);
     const Planes<T> base(p.Ubase ? p.Ubase : p.U, plane);
@@ -69,10 +70,12 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
         if (FINAL) kick(Un, p, dt, i, j, TWOD);
         if (own) {
             out.store((unsigned)(j * p.nx + i), Un);
-            if (FINAL) {
+            if constexpr (FINAL && TWOD) {
+                smax = fmax(smax, checked_rate(Un, idx, idy, bad));
+            } else if constexpr (FINAL) {
                 const Prim<T> wn = to_prim(Un);
                 smax = fmax(smax, signal_rate<T, TWOD>(wn, idx, idy));
-                bad = bad || !physical(wn);
+                bad |= !physical(wn);
             }
         }
     };
@@ -80,12 +83,12 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
     if constexpr (!TWOD) {
         const Cons<T> C0 = in.load((unsigned)gc);
         const Prim<T> W0 = to_prim(C0);
-        const Prim<T> s = mc_slope(lane_shift<-1>(W0), W0, lane_shift<+1>(W0));
-        const Cons<T> F = kt_flux_x(half_step(W0, T(0.5), s), lane_shift<+1>(half_step(W0, T(-0.5), s)));
+        const Prim<T> s = mc_half_slope(lane_shift<-1>(W0), W0, lane_shift<+1>(W0));
+        const Cons<T> F = kt_flux2_x(plus(W0, s), lane_shift<+1>(sub(W0, s)));
         const Cons<T> Fm = lane_shift<-1>(F);
         finish(update(FINAL ? base.load((unsigned)gc) : C0, cx, F, Fm), c, 0);
     } else {
-        const T cy = T(h / p.dy);
+        const T cy = T(0.5 * h / p.dy);
         const int y0 = sy * p.ty, y1 = min(y0 + p.ty, p.ny);
         auto load_row = [&](const Planes<T>& P, int r) -> Cons<T> {
             return P.load((unsigned)(map_near(r, p.ny, p.bcy) * p.nx + gc));  // ny >= 2
@@ -101,20 +104,19 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
         // one row: Wm row r-1 (refilled with row r+2), W0 row r, Wp row r+1;
         // Cm, C0 the conserved forms of rows r-1 and r
         auto row = [&](int r, Prim<T>& Wm, const Prim<T>& W0, const Prim<T>& Wp, Cons<T>& Cm, const Cons<T>& C0) {
-            const Cons<T> Unext = (r + 2 <= y1 + 1) ? load_row(in, r + 2) : Cons<T>{};
-            const Prim<T> sxv = mc_slope(lane_shift<-1>(W0), W0, lane_shift<+1>(W0));
-            const Prim<T> syv = mc_slope(Wm, W0, Wp);
-            const Prim<T> ylo = half_step(W0, T(-0.5), syv);
+            const Cons<T> Unext = load_row(in, min(r + 2, y1 + 1));  // past the end: a row already read
+            const Prim<T> sxv = mc_half_slope(lane_shift<-1>(W0), W0, lane_shift<+1>(W0));
+            const Prim<T> syv = mc_half_slope(Wm, W0, Wp);
+            const Prim<T> ylo = sub(W0, syv);
             if (r >= y0) {
-                const Cons<T> G = swap(kt_flux_x(swap(yhi_prev), swap(ylo)));  // face r - 1/2
+                const Cons<T> G = swap(kt_flux2_x(swap(yhi_prev), swap(ylo)));  // face r - 1/2
                 if (r > y0) {
                     finish({acc.r - cy * G.r, acc.mx - cy * G.mx, acc.my - cy * G.my, acc.exx - cy * G.exx,
                             acc.exy - cy * G.exy, acc.eyy - cy * G.eyy},
                            c, r - 1);
                 }
                 if (r < y1) {
-                    const Cons<T> F =
-                        kt_flux_x(half_step(W0, T(0.5), sxv), lane_shift<+1>(half_step(W0, T(-0.5), sxv)));
+                    const Cons<T> F = kt_flux2_x(plus(W0, sxv), lane_shift<+1>(sub(W0, sxv)));
                     const Cons<T> Fm = lane_shift<-1>(F);
                     const Cons<T> B = kOwnBase ? C0 : load_row(base, r);
                     acc = {B.r - cx * (F.r - Fm.r) + cy * G.r,           B.mx - cx * (F.mx - Fm.mx) + cy * G.mx,
@@ -122,11 +124,9 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
                            B.exy - cx * (F.exy - Fm.exy) + cy * G.exy, B.eyy - cx * (F.eyy - Fm.eyy) + cy * G.eyy};
                 }
             }
-            yhi_prev = half_step(W0, T(0.5), syv);
-            if (r + 2 <= y1 + 1) {
-                Wm = to_prim(Unext);
-                if (kOwnBase) Cm = Unext;
-            }
+            yhi_prev = plus(W0, syv);
+            Wm = to_prim(Unext);  // row r + 2 takes the place of row r - 1
+            if (kOwnBase) Cm = Unext;
         };
 
         for (int r = y0 - 1; r <= y1; r += 3) {
