@@ -298,6 +298,27 @@ def copy_probe(nbytes=1 << 30):
     log(f"copy probe: {nbytes} bytes read + {nbytes} written per launch")
 
 
+def device_copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Bytes moved per second (read + write) by a plain 1 GiB device-to-device
+    copy, timed with HIP events: the practical HBM ceiling beside the
+    8 TB/s published peak."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes * reps / secs / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +378,8 @@ def main():
         del g
         torch.cuda.empty_cache()
 
+    copy_gbs = device_copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     f64 = res["f64"]
     value = K * cells / f64["secs"]
     achieved = f64["bpc"] * cells / f64["kernel_s"] / 1e9
@@ -382,7 +405,8 @@ def main():
                      "kernel": "sweep_kernel<double, 2-D>", "kernel_ms": f64["kernel_s"] * 1e3,
                      "kernel_source_hash": sweep_source_hash(),
                      "algorithmic_bytes_per_launch": f64["bpc"] * cells,
-                     "valu": valu_summary(counters, f64["kernel_s"], cells)},
+                     "valu": valu_summary(counters, f64["kernel_s"], cells),
+                     "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs},
     }
     if "f32" in res:
         f32 = res["f32"]

@@ -32,7 +32,7 @@ namespace csh {
 template <bool TWOD, int STAGE>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (STAGE == 4) {  // interior cells
         if (t >= (int64_t)a.nx * a.ny) return;
         gather_cell<TWOD>(a, (int)(t % a.nx), (int)(t / a.nx));

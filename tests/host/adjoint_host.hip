@@ -121,3 +121,9 @@ extern "C" void host_init_adjoint(int64_t n, const double* W, const double* lamU
         for (int m = 0; m < 6; ++m) lamW[m * n + c] = v[m];
     }
 }
+
+// the adjoint kernels' workgroup renumbering, for the bijection test
+extern "C" unsigned host_xcd_block(unsigned b, unsigned nb)
+{
+    return csh::xcd_block(b, nb);
+}

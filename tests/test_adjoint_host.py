@@ -28,6 +28,8 @@ def lib():
         L.host_adjoint_step.argtypes = sig
         L.host_step.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 7 + [_D, _D]
         L.host_init_adjoint.argtypes = [ctypes.c_int64, _D, _D, _D]
+        L.host_xcd_block.argtypes = [ctypes.c_uint, ctypes.c_uint]
+        L.host_xcd_block.restype = ctypes.c_uint
         _lib = L
     return _lib
 
@@ -136,3 +138,15 @@ def test_init_adjoint_is_transpose_of_cons():
     lib().host_init_adjoint(W[0].size, p(np.ascontiguousarray(W)), p(np.ascontiguousarray(lamU)), p(out))
     rhs = float((out * d).sum())
     assert abs(lhs - rhs) <= 1e-8 * abs(lhs)
+
+
+@pytest.mark.parametrize("nb", [1, 2, 7, 8, 9, 15, 16, 17, 1031, 1032, 1033])
+def test_xcd_renumbering_is_a_bijection(nb):
+    """The adjoint kernels' XCD-aware workgroup numbering covers every logical
+    workgroup once, and hands each XCD (b % 8) one contiguous range."""
+    f = lib().host_xcd_block
+    logical = [f(b, nb) for b in range(nb)]
+    assert sorted(logical) == list(range(nb))
+    for x in range(8):
+        mine = sorted(logical[b] for b in range(x, nb, 8))
+        assert mine == list(range(mine[0], mine[0] + len(mine))) if mine else True
