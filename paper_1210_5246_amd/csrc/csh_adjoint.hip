@@ -6,8 +6,8 @@
 // states from itself and its four neighbours; every face flux uses the high
 // state of one extended cell and the low state of the next; the update of an
 // interior cell uses its four faces.  The reverse pass follows the same
-// structure in four kernels, with fixed slots instead of atomics so the
-// result is deterministic:
+// structure in four steps (five kernels: the third runs as two), with fixed
+// slots instead of atomics so the result is deterministic:
 //   1. faces:  recompute the face states of every extended cell -> FS
 //   2. hll:    per face, lam' = K^T lam^{n+1} (kick), flux adjoint
 //              dt/dx (lam'_{i+1} - lam'_i), HLL vjp -> adjoints of the two face
@@ -20,6 +20,9 @@
 //   4. gather: per interior cell, sum the slots that land on each padded
 //              position, fold the padded positions that the boundary mapping
 //              sends to this cell, chain through W(U) and add lam' itself.
+//
+// The kernels take their workgroup numbers XCD-aware (xcd_block), so the rows
+// a thread reads from its y neighbours sit in the same L2.
 #include <string>
 
 #include "csh_adjoint.h"
