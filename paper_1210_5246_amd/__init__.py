@@ -102,9 +102,14 @@ def _check(code: int):
         raise CshError(code, msg)
 
 
-def _dev(t: torch.Tensor, dtype) -> int:
+def _dev(t: torch.Tensor, dtype, numel: int | None = None, at_least: bool = False) -> int:
+    """Device pointer of a contiguous GPU tensor of ``dtype``; with ``numel``
+    the tensor must hold exactly (``at_least``: at least) that many elements,
+    since the kernels index it from the handle's sizes alone."""
     if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
         raise ValueError(f"expected a contiguous {dtype} GPU tensor, got {t.dtype} on {t.device}")
+    if numel is not None and (t.numel() < numel if at_least else t.numel() != numel):
+        raise ValueError(f"expected {'at least ' if at_least else ''}{numel} elements, got {t.numel()}")
     return t.data_ptr()
 
 
@@ -134,6 +139,7 @@ class Grid:
         self.shape = tuple(W.shape)
         self.nx, self.ny, self.dx, self.dy = nx, ny, float(dx), float(dy)
         self.U = torch.empty_like(W)
+        self.n = 6 * nx * ny  # elements of a state
         self._h = _vp()
         code = lib().csh_init_state(ctypes.byref(self._h), nx, ny, self.dx, self.dy, int(bc[0]), int(bc[1]),
                                     self.code, _dev(W, W.dtype), _dev(self.U, W.dtype), _stream())
@@ -151,7 +157,7 @@ class Grid:
     def set_state(self, W: torch.Tensor, U: torch.Tensor | None = None) -> torch.Tensor:
         """Primitive fields -> conserved state (default into ``self.U``) on this handle."""
         U = self.U if U is None else U
-        _check(lib().csh_set_state(self._h, _dev(W, self.dtype), _dev(U, self.dtype)))
+        _check(lib().csh_set_state(self._h, _dev(W, self.dtype, self.n), _dev(U, self.dtype, self.n)))
         return U
 
     def set_scheme(self, scheme: str):
@@ -165,7 +171,7 @@ class Grid:
         (x0, y0) is the lower-left corner of the grid, the region [-X, X] x [-Y, Y]."""
         U = self.U if U is None else U
         out = (ctypes.c_double * m_max)()
-        _check(lib().csh_fourier_amplitudes(self._h, _dev(U, self.dtype), float(x0), float(y0), float(X), float(Y),
+        _check(lib().csh_fourier_amplitudes(self._h, _dev(U, self.dtype, self.n), float(x0), float(y0), float(X), float(Y),
                                             int(m_max), out))
         return list(out)
 
@@ -176,13 +182,13 @@ class Grid:
         """One sweep; returns the new state (a new tensor unless ``out`` is given)."""
         U = self.U if U is None else U
         out = torch.empty_like(U) if out is None else out
-        _check(lib().csh_step(self._h, float(dt), _dev(U, self.dtype), _dev(out, self.dtype)))
+        _check(lib().csh_step(self._h, float(dt), _dev(U, self.dtype, self.n), _dev(out, self.dtype, self.n)))
         return out
 
     def max_signal_speed(self, U: torch.Tensor | None = None) -> float:
         U = self.U if U is None else U
         s = ctypes.c_double()
-        _check(lib().csh_max_signal_speed(self._h, _dev(U, self.dtype), ctypes.byref(s)))
+        _check(lib().csh_max_signal_speed(self._h, _dev(U, self.dtype, self.n), ctypes.byref(s)))
         return s.value
 
     def last_signal_speed(self) -> float:
@@ -195,7 +201,7 @@ class Grid:
         U = self.U if U is None else U
         Fx = torch.empty((6, self.ny, self.nx + 1), dtype=self.dtype, device=U.device)
         Fy = torch.empty((6, self.ny + 1, self.nx), dtype=self.dtype, device=U.device) if self.ny > 1 else None
-        _check(lib().csh_fluxes(self._h, float(dt), _dev(U, self.dtype), _dev(Fx, self.dtype),
+        _check(lib().csh_fluxes(self._h, float(dt), _dev(U, self.dtype, self.n), _dev(Fx, self.dtype),
                                 _dev(Fy, self.dtype) if Fy is not None else None))
         if self.ny == 1:
             return Fx.reshape(6, self.nx + 1), None
@@ -212,8 +218,8 @@ class Grid:
                 work = self._work = torch.empty_like(U)
         if dt_log is None:
             dt_log = torch.empty(max(nsteps, 1), dtype=torch.float64, device=U.device)
-        _check(lib().csh_run_cfl(self._h, int(nsteps), float(cfl), float(t_end), _dev(U, self.dtype),
-                                 _dev(work, self.dtype), _dev(dt_log, torch.float64)))
+        _check(lib().csh_run_cfl(self._h, int(nsteps), float(cfl), float(t_end), _dev(U, self.dtype, self.n),
+                                 _dev(work, self.dtype, self.n), _dev(dt_log, torch.float64, nsteps, True)))
         return dt_log[:nsteps]
 
     def run_dts(self, dts: torch.Tensor, U: torch.Tensor | None = None, work: torch.Tensor | None = None):
@@ -223,23 +229,23 @@ class Grid:
             work = getattr(self, "_work", None)
             if work is None or work.shape != U.shape or work.dtype != U.dtype:
                 work = self._work = torch.empty_like(U)
-        _check(lib().csh_run_dts(self._h, int(dts.numel()), _dev(dts, torch.float64), _dev(U, self.dtype),
-                                 _dev(work, self.dtype)))
+        _check(lib().csh_run_dts(self._h, int(dts.numel()), _dev(dts, torch.float64), _dev(U, self.dtype, self.n),
+                                 _dev(work, self.dtype, self.n)))
         return U
 
     def adjoint_step(self, dt: float, U: torch.Tensor, lam_next: torch.Tensor,
                      out: torch.Tensor | None = None) -> torch.Tensor:
         out = torch.empty_like(lam_next) if out is None else out
-        _check(lib().csh_adjoint_step(self._h, float(dt), _dev(U, self.dtype), _dev(lam_next, self.dtype),
-                                      _dev(out, self.dtype)))
+        _check(lib().csh_adjoint_step(self._h, float(dt), _dev(U, self.dtype, self.n),
+                                      _dev(lam_next, self.dtype, self.n), _dev(out, self.dtype, self.n)))
         return out
 
 
     def init_state_adjoint(self, W: torch.Tensor, lam_U: torch.Tensor,
                            out: torch.Tensor | None = None) -> torch.Tensor:
         out = torch.empty_like(lam_U) if out is None else out
-        _check(lib().csh_init_state_adjoint(self._h, _dev(W, self.dtype), _dev(lam_U, self.dtype),
-                                            _dev(out, self.dtype)))
+        _check(lib().csh_init_state_adjoint(self._h, _dev(W, self.dtype, self.n), _dev(lam_U, self.dtype, self.n),
+                                            _dev(out, self.dtype, self.n)))
         return out
 
 
@@ -264,6 +270,7 @@ class Grid3:
         self.nz, self.ny, self.nx = (int(x) for x in W.shape[1:])
         self.h = tuple(float(x) for x in h)
         self.U = torch.empty_like(W)
+        self.n = 10 * self.nx * self.ny * self.nz  # elements of a state
         self._h = _vp()
         _check3(lib().csh3_init_state(ctypes.byref(self._h), self.nx, self.ny, self.nz, *self.h, int(bc[0]),
                                       int(bc[1]), int(bc[2]), _dev(W, torch.float64),
@@ -278,13 +285,13 @@ class Grid3:
     def step(self, dt: float, U: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
         U = self.U if U is None else U
         out = torch.empty_like(U) if out is None else out
-        _check3(lib().csh3_step(self._h, float(dt), _dev(U, torch.float64), _dev(out, torch.float64)))
+        _check3(lib().csh3_step(self._h, float(dt), _dev(U, torch.float64, self.n), _dev(out, torch.float64, self.n)))
         return out
 
     def max_signal_speed(self, U: torch.Tensor | None = None) -> float:
         U = self.U if U is None else U
         s = ctypes.c_double()
-        _check3(lib().csh3_max_signal_speed(self._h, _dev(U, torch.float64), ctypes.byref(s)))
+        _check3(lib().csh3_max_signal_speed(self._h, _dev(U, torch.float64, self.n), ctypes.byref(s)))
         return s.value
 
     def last_signal_speed(self) -> float:
@@ -318,6 +325,8 @@ class Batch:
         import numpy as np
         self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         self.ntubes = int(self.offsets.size - 1)
+        if self.ntubes >= 1 and W.numel() != 6 * int(self.offsets[-1]):
+            raise ValueError(f"W must hold 6 x offsets[-1] = {6 * int(self.offsets[-1])} elements")
         self.U = torch.empty_like(W)
         self._work = torch.empty_like(W)
         self._h = _vp()
@@ -335,7 +344,8 @@ class Batch:
         if dt_out is None:
             dt_out = torch.empty((self.ntubes, max(nsteps, 1)), dtype=torch.float64, device=self.U.device)
         _check(lib().csh_batch_run(self._h, int(nsteps), float(cfl), _dev(self.U, torch.float64),
-                                   _dev(self._work, torch.float64), _dev(dt_out, torch.float64), int(threads)))
+                                   _dev(self._work, torch.float64),
+                                   _dev(dt_out, torch.float64, self.ntubes * nsteps, True), int(threads)))
         return dt_out
 
     def autotune(self, probe_steps: int = 8, cfl: float = 0.8) -> int:

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs a)
     constexpr int NW = NT / 64;
     __shared__ int s_q;
     __shared__ double red[NW];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_in_block();  // wave-uniform chunk loop
     const size_t plane = (size_t)a.N;
 
     for (;;) {
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs a)
                     store_cons(B, plane, (size_t)c, Un);
                     const Prim<double> wn = to_prim(Un);
                     smax = fmax(smax, signal_rate<double, false>(wn, idx, 0.0));
-                    bad = bad || !physical(wn);
+                    bad |= !physical(wn);
                 }
             }
             s = block_max<NT>(smax, red);  // its barriers also order this step's stores before the next step's loads
