@@ -109,3 +109,42 @@ def test_3d_nonphysical_input_rejected():
     say("3d nonphysical init")
     with pytest.raises(csh.NonPhysicalState):
         gpu(W, h, (0, 0, 0))
+
+
+def test_3d_256_benchmark_configuration():
+    """The benchmark's state and launch configuration (periodic 256^3, 32-plane
+    segments, 60-column strips): one step compared cell by cell with the oracle
+    on 3000 random cells plus cells on the strip, row and segment seams and the
+    periodic wrap; then ten device-timed steps keep every conserved total to
+    round-off (periodic boundaries: the face fluxes telescope)."""
+    n = 256
+    w = wl.periodic3(n, seed=7)
+    say("3d 256^3 benchmark state: one step, sampled cells")
+    G = gpu(w.W, w.h, w.bc)
+    g = oracle.Grid3(n, n, n, w.h[0], w.h[1], w.h[2], w.bc)
+    U0 = oracle.cons3_field(w.W)
+    s_o = oracle.max_signal_speed3(g, U0)
+    assert G.max_signal_speed() == pytest.approx(s_o, rel=1e-13)
+    dt = 0.8 / s_o
+    out = G.step(dt).cpu().numpy().reshape(10, -1)
+    r = np.random.default_rng(76)
+    cells = set(r.integers(0, n ** 3, size=3000).tolist())
+    for x in (0, 1, 58, 59, 60, 61, 119, 120, 238, 239, 240, 254, 255):
+        for y, z in ((0, 0), (255, 31), (128, 32), (1, 255), (37, 63), (200, 64), (254, 224), (100, 223)):
+            cells.add((z * n + y) * n + x)
+    cells = np.array(sorted(cells), dtype=np.int64)
+    ref = oracle.step3_cells(g, dt, U0, cells).T          # [10, ncells]
+    got = out[:, cells]
+    scale = np.abs(U0.reshape(10, -1)).max(axis=1)
+    for m in range(10):
+        if m in POSITIVE:
+            e = np.abs(got[m] - ref[m]) / np.abs(ref[m])
+        else:
+            e = np.abs(got[m] - ref[m]) / max(scale[m], scale[1:4].max())
+        assert e.max() <= 1e-12, (m, float(e.max()))
+    say("3d 256^3: ten device-timed steps, conservation")
+    tot0 = U0.reshape(10, -1).sum(axis=1)
+    mag = np.abs(U0.reshape(10, -1)).sum(axis=1)
+    G.run_cfl(10, 0.8)
+    tot1 = G.U.reshape(10, -1).sum(dim=1).cpu().numpy()
+    assert np.all(np.abs(tot1 - tot0) <= 1e-12 * mag), (tot1 - tot0) / mag
