@@ -33,6 +33,7 @@ BYTES_PER_CELL_3D_MIN = 160
 BYTES_PER_CELL_3D_DESIGN = 640
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
+VALU_ISSUE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-instructions per second, 1e12
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -66,9 +67,15 @@ def valu_summary(t, kernel_s, cells):
     if not v:
         return None
     tflops = v["fp64_flops_per_launch"] / kernel_s / 1e12
+    # the ALU view: VALU lane-instructions issued per second against the issue
+    # peak of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 instruction
+    # per 4 cycles per SIMD)
+    issue = v["valu_lane_instructions_per_cell"] * cells / kernel_s / 1e12
     return {"valu_busy": v["valu_busy"], "lane_instructions_per_cell": v["valu_lane_instructions_per_cell"],
             "fp64_flops_per_cell": v["fp64_flops_per_cell"], "fp64_tflops": tflops,
-            "fp64_peak_tflops": FP64_PEAK_TFLOPS, "fp64_frac": tflops / FP64_PEAK_TFLOPS}
+            "fp64_peak_tflops": FP64_PEAK_TFLOPS, "fp64_frac": tflops / FP64_PEAK_TFLOPS,
+            "issue_tlane_instr_per_s": issue, "issue_peak_tlane_instr_per_s": VALU_ISSUE_PEAK_T,
+            "issue_frac": issue / VALU_ISSUE_PEAK_T}
 
 
 def log(*a):
