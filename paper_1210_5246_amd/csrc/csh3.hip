@@ -131,6 +131,7 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
     // plane r): one wavefront per SIMD hides the memory latency this way.
     V10 Wa = prim(ld(gj0, z0 - 2)), C0 = ld(gj0, z0 - 1), Wb = prim(C0);
     V10 Cz = ld(gj0, z0), Cym = ld(gjm, z0 - 1), Cyp = ld(gjp, z0 - 1), zhi_prev, acc;
+    V10 Cym1 = ld(gjm, z0), Cyp1 = ld(gjp, z0);  // neighbour rows one plane ahead
 #pragma unroll
     for (int m = 0; m < NV; ++m) zhi_prev.v[m] = acc.v[m] = 0.0;
 
@@ -138,7 +139,9 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
     // Ordered so that each slope and face pair dies as early as possible.
     auto plane_step = [&](int r, V10& Wm, const V10& W0) {
         // the next step's loads first
-        const V10 Cz_n = ld(gj0, r + 2), Cym_n = ld(gjm, r + 1), Cyp_n = ld(gjp, r + 1);
+        // the neighbour rows of plane r + 2, loaded with this row's own plane r + 2
+        // (the neighbouring wavefronts load them as their own rows in the same step)
+        const V10 Cz_n = ld(gj0, r + 2), Cym_n = ld(gjm, r + 2), Cyp_n = ld(gjp, r + 2);
         const double ir = rcp(W0.v[0]);
         double a3[3];  // fast speeds sqrt(3 P_kk / rho)
         auto coef = [&](int k, double k2, double& chi, double& clo) {
@@ -219,8 +222,10 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
         Wm = Wp;
         C0 = Cz;
         Cz = Cz_n;
-        Cym = Cym_n;
-        Cyp = Cyp_n;
+        Cym = Cym1;
+        Cyp = Cyp1;
+        Cym1 = Cym_n;
+        Cyp1 = Cyp_n;
     };
 
     for (int r = z0 - 1; r <= z1; r += 2) {
