@@ -37,8 +37,9 @@ VALU_ISSUE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-instructions per second,
 
 
 PROFILES = os.path.join(ROOT, "profiles")
+# the sweep kernel's sources and the file that sets its launch shape (rows per segment)
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_1210_5246_amd", "csrc", f)
-                 for f in ("csh_fwd.hip", "csh_device.h", "csh_internal.h")]
+                 for f in ("csh_fwd.hip", "csh_device.h", "csh_internal.h", "csh_api.hip")]
 
 
 def sweep_source_hash() -> str:

@@ -45,14 +45,25 @@ int rows_per_segment(int nx, int ny)
         const int v = std::atoi(e);
         if (v >= 1) return v;
     }
-    // about 6144 wavefronts: three rounds of the 2048 that fit at once (2 per
-    // SIMD at the sweep's register count), segments of 4..96 rows; fewer,
-    // longer segments re-trace fewer halo rows (measured on 4096^2: 40-48 rows
-    // best, within 2% of 32 and 96)
+    // The segment length that minimises the critical path of the busiest SIMD:
+    // ceil(wavefronts / 1024 SIMDs) wavefronts in turn, each marching its rows
+    // plus the two halo rows it re-traces.  Fitted on square grids of 256^2 to
+    // 4096^2 (measured: within a few % of the best length at every size, where
+    // a fixed wavefront count had lost up to 38% at 1024^2 to halo rows).
+    // Lengths below 8 rows only when 8 would leave fewer wavefronts than CUs.
     const long strips = (nx + csh::kStrip - 1) / csh::kStrip;
-    const long t = ((long)ny * strips + 3072) / 6144;
-    const int ty = (int)std::max(4L, std::min(96L, t));
-    return ty;
+    auto waves = [&](int t) { return strips * ((ny + t - 1) / t); };
+    const int lo = waves(8) >= 256 ? 8 : 4;
+    int best = lo;
+    long best_cost = -1;
+    for (int t = lo; t <= 96; ++t) {
+        const long cost = ((waves(t) + 1023) / 1024) * (t + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = t;
+        }
+    }
+    return best;
 }
 
 // Riemann solver of the characteristic sweep
