@@ -13,9 +13,43 @@ this module only sequences the calls and holds the checkpoints.
 """
 from __future__ import annotations
 
+from collections import OrderedDict
+
 import torch
 
 from . import BC_PERIODIC, Grid
+
+# Grid handles reused by consecutive sweeps with the same geometry (the usual
+# pattern of an optimisation loop): the handle's captured graph, reduction
+# slots and adjoint workspace are then set up once.  At most _CACHE_SIZE
+# handles are kept (least recently used dropped); clear_cache() frees them.
+_CACHE_SIZE = 2
+_cache: OrderedDict = OrderedDict()
+
+
+def clear_cache() -> None:
+    """Drop the grid handles kept for reuse."""
+    _cache.clear()
+
+
+def _grid(W0: torch.Tensor, dx: float, dy: float, bc, potential, checkpoint_every: int) -> Grid:
+    key = (tuple(W0.shape), W0.dtype, str(W0.device), float(dx), float(dy), tuple(int(b) for b in bc),
+           None if potential is None else tuple(float(x) for x in potential))
+    g = _cache.pop(key, None)
+    if g is None:
+        g = Grid(W0, dx, dy, bc)
+        if potential is not None:
+            g.set_potential(*potential)
+    else:
+        g.set_state(W0)
+    _cache[key] = g
+    while len(_cache) > _CACHE_SIZE:
+        _cache.popitem(last=False)
+    # one timestep log buffer per handle: the graph captured for a segment
+    # length is reused as long as its buffers are the same
+    if getattr(g, "_seg_log", None) is None or g._seg_log.numel() < checkpoint_every:
+        g._seg_log = torch.empty(checkpoint_every, dtype=torch.float64, device=W0.device)
+    return g
 
 
 class AdjointSweep(torch.autograd.Function):
@@ -24,30 +58,31 @@ class AdjointSweep(torch.autograd.Function):
     @staticmethod
     def forward(ctx, W0: torch.Tensor, dx: float, dy: float, bc, nsteps: int, checkpoint_every: int,
                 cfl: float = 0.8, potential=None, dts=None):
-        g = Grid(W0.detach().contiguous(), dx, dy, bc)
-        if potential is not None:
-            g.set_potential(*potential)
         K = max(1, int(checkpoint_every))
+        g = _grid(W0.detach().contiguous(), dx, dy, bc, potential, K)
         U = g.U
-        log = torch.empty(K, dtype=torch.float64, device=U.device)  # one buffer: the captured graph is reused
+        log = g._seg_log
         ckpts, seg_dts = [], []
         if dts is not None:  # replay a given timestep list
             dts = [float(d) for d in dts]
             assert len(dts) == nsteps
+        else:
+            dts_dev = torch.empty(max(nsteps, 1), dtype=torch.float64, device=U.device)
         done = 0
         while done < nsteps:
             k = min(K, nsteps - done)
             ckpts.append(U.clone())
             if dts is None:
-                seg = g.run_cfl(k, cfl, U=U, dt_log=log).cpu().tolist()
+                dts_dev[done:done + k].copy_(g.run_cfl(k, cfl, U=U, dt_log=log))  # stays on the device
             else:
-                seg = dts[done:done + k]
                 V = U
-                for dt in seg:
+                for dt in dts[done:done + k]:
                     V = g.step(dt, V)
                 U.copy_(V)
-            seg_dts.append(seg)
             done += k
+        if dts is None:
+            dts = dts_dev[:nsteps].cpu().tolist()  # one host synchronisation for the whole run
+        seg_dts = [dts[i:i + K] for i in range(0, nsteps, K)]
         ctx.grid = g
         ctx.ckpts = ckpts
         ctx.seg_dts = seg_dts
