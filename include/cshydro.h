@@ -92,8 +92,10 @@ int csh_set_state(csh_grid *h, const void *W, void *U);
  *     local-speed flux H = (F(u-) + F(u+))/2 - a/2 (u+ - u-), a = max |u_n| +
  *     sqrt(3 P_nn / rho) over the two face states, faces reconstructed by
  *     component-wise MC-limited linear primitive profiles, two stages of the
- *     Runge-Kutta midpoint rule per step, then the kick.  Two launches per step;
- *     the first call allocates one state-sized stage buffer the handle keeps.
+ *     Runge-Kutta midpoint rule per step, then the kick.  On a 2-D grid both
+ *     stages run in one launch (the intermediate state is never stored); on a
+ *     1-D grid two launches, and the first call allocates one state-sized
+ *     stage buffer the handle keeps.
  * csh_fluxes returns the faces of either characteristic sweep and CSH_ERR_ARG
  * under CSH_SCHEME_KT; csh_adjoint_step is that of CSH_SCHEME_MUSCL_HLL and
  * returns CSH_ERR_ARG under the other schemes.  Synchronises.

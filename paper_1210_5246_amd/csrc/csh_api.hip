@@ -28,7 +28,7 @@ struct csh_grid {
     double* adj_ws = nullptr;       // adjoint workspace, allocated on first use
     size_t adj_ws_n = 0;
     int scheme = CSH_SCHEME_MUSCL_HLL;
-    void* kt_buf = nullptr;         // stage state of the Kurganov-Tadmor scheme
+    void* kt_buf = nullptr;         // stage state of the 1-D Kurganov-Tadmor scheme
     double* fourier_ws = nullptr;   // partial sums + amplitudes of csh_fourier_amplitudes
     // cached graph of csh_run_cfl / csh_run_dts
     hipGraphExec_t exec = nullptr;
@@ -110,12 +110,16 @@ hipError_t enqueue_step(csh_grid* h, const void* U, void* Un, int dev_dt, double
     a.s_in = h->phase;
     a.s_out = (h->phase + 1) % 3;
     a.s_reset = (h->phase + 2) % 3;
+    if (h->scheme == CSH_SCHEME_KT && h->ny > 1) {
+        h->phase = a.s_out;
+        return csh::launch_kt_fused<T>(a, s);
+    }
     if (h->scheme == CSH_SCHEME_KT) {
-        // stage 1: U -> stage buffer over dt/2; records dt in slot s_in
+        // 1-D: stage 1: U -> stage buffer over dt/2; records dt in slot s_in
         auto a1 = a;
         a1.Unew = static_cast<T*>(h->kt_buf);
         a1.dt_log = nullptr;
-        hipError_t e = csh::launch_kt<T>(a1, h->ny > 1, false, s);
+        hipError_t e = csh::launch_kt<T>(a1, false, s);
         if (e != hipSuccess) return e;
         // stage 2: fluxes of the stage state, update from U over dt
         a.U = static_cast<const T*>(h->kt_buf);
@@ -125,7 +129,7 @@ hipError_t enqueue_step(csh_grid* h, const void* U, void* Un, int dev_dt, double
             a.dt_in = &h->slots[h->phase].dt;
         }
         h->phase = a.s_out;
-        return csh::launch_kt<T>(a, h->ny > 1, true, s);
+        return csh::launch_kt<T>(a, true, s);
     }
     h->phase = a.s_out;
     return csh::launch_step<T>(a, h->ny > 1, false, solver_of(h), s);
@@ -242,7 +246,7 @@ extern "C" int csh_set_scheme(csh_grid* h, int scheme)
     if (!h) return csh_fail(CSH_ERR_ARG, "h is NULL");
     if (scheme != CSH_SCHEME_MUSCL_HLL && scheme != CSH_SCHEME_KT && scheme != CSH_SCHEME_MUSCL_HLLC)
         return csh_fail(CSH_ERR_ARG, "unknown scheme");
-    if (scheme == CSH_SCHEME_KT && !h->kt_buf) {
+    if (scheme == CSH_SCHEME_KT && h->ny == 1 && !h->kt_buf) {  // the 1-D stage buffer
         const size_t bytes = 6 * (size_t)h->nx * h->ny * (h->dtype == CSH_F64 ? 8 : 4);
         CSH_HIP(hipStreamSynchronize(h->stream));
         CSH_HIP(hipMalloc(&h->kt_buf, bytes));

@@ -53,10 +53,16 @@ hipError_t launch_maxspeed(const T* U, int nx, int ny, double dx, double dy, Slo
 
 hipError_t launch_reset(Slot* slots, int nslots, double t0, hipStream_t s);
 
-// Kurganov-Tadmor stage: first (half step into the stage buffer, records dt in
-// slots[s_in].dt) or final (full step from Ubase with the stage state's fluxes)
+// Kurganov-Tadmor stage on a 1-D grid: first (half step into the stage
+// buffer, records dt in slots[s_in].dt) or final (full step from Ubase with
+// the stage state's fluxes)
 template <typename T>
-hipError_t launch_kt(const StepArgs<T>& a, bool twod, bool final_stage, hipStream_t s);
+hipError_t launch_kt(const StepArgs<T>& a, bool final_stage, hipStream_t s);
+
+// Kurganov-Tadmor step on a 2-D grid, both stages in one launch (its own
+// strips and row segments; the arguments' decomposition fields are ignored)
+template <typename T>
+hipError_t launch_kt_fused(StepArgs<T> a, hipStream_t s);
 
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);

@@ -2,9 +2,11 @@
 
 Same bars as the characteristic sweep: max relative error (per-field metric of
 tests/parity.py) <= 1e-12 after one step and <= 1e-10 after 100 steps, on
-ragged shapes spanning several 60-column strips and row segments, both
-boundary kinds, 1-D and 2-D, with and without the external potential; the
-full-size disc (4096^2) is compared on every cell after one step.
+ragged shapes spanning several column strips (56 columns per wavefront in
+2-D, 60 in 1-D) and row segments, around the strip edges, both boundary
+kinds in each direction, 1-D and 2-D, with and without the external
+potential; the full-size disc (4096^2) is compared on every cell after one
+step.
 """
 import sys
 
@@ -52,8 +54,8 @@ def rect_periodic(nx, ny, seed, bc=(0, 0)):
     return w
 
 
-@pytest.mark.parametrize("shape", [(250, 77), (61, 5), (7, 130), (1, 3), (2, 2)])
-@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
+@pytest.mark.parametrize("shape", [(250, 77), (61, 5), (7, 130), (1, 3), (2, 2), (56, 4), (57, 9), (113, 33)])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
 def test_kt_one_step_2d(shape, bc):
     nx, ny = shape
     w = rect_periodic(nx, ny, 41, bc)
