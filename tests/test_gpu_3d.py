@@ -62,6 +62,22 @@ def test_3d_one_step(n, bc):
     assert G.last_signal_speed() == pytest.approx(oracle.max_signal_speed3(g, ref), rel=1e-13)
 
 
+@pytest.mark.parametrize("planes", [1, 2, 3])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
+def test_3d_short_segments(planes, bc, monkeypatch):
+    """z segments shorter than the march's halo planes (the CSH_PLANES
+    override, read at each launch)."""
+    monkeypatch.setenv("CSH_PLANES", str(planes))
+    W, g, h = workload((37, 11, 13), 73, bc)
+    say("3d one step, planes per segment", planes, bc)
+    G = gpu(W, h, bc)
+    U0 = oracle.cons3_field(W)
+    dt = 0.8 / oracle.max_signal_speed3(g, U0)
+    ref = oracle.step3(g, dt, U0)
+    assert rel_err(G.step(dt).cpu().numpy(), ref) <= 1e-12
+    assert G.last_signal_speed() == pytest.approx(oracle.max_signal_speed3(g, ref), rel=1e-13)
+
+
 def test_3d_thirty_steps_device_dt():
     W, g, h = workload((40, 36, 32), 72, (0, 1, 0))
     say("3d 40x36x32 x 30 (oracle first)")

@@ -69,6 +69,24 @@ def test_kt_one_step_2d(shape, bc):
     assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
 
 
+@pytest.mark.parametrize("rows", [1, 2, 3, 5])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
+def test_kt_short_segments(rows, bc, monkeypatch):
+    """Row segments shorter than the fused march's halo (stage 1 runs 4 rows
+    ahead of stage 2's owned rows; the CSH_KT_ROWS override, read at each
+    launch): the ghost-row copies and the ring slots at every segment edge."""
+    monkeypatch.setenv("CSH_KT_ROWS", str(rows))
+    w = rect_periodic(127, 23, 43, bc)
+    say("kt one step, rows per segment", rows, bc)
+    g = kt_grid(w)
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    dt = 0.8 / oracle.max_signal_speed(og, U0)
+    ref = oracle.step_kt(og, dt, U0)
+    assert max_rel_error(g.step(dt).cpu().numpy(), ref) <= TOL1
+    assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 59, 60, 61, 256, 1000])
 @pytest.mark.parametrize("bc", [0, 1])
 def test_kt_one_step_1d(n, bc):

@@ -70,7 +70,7 @@ def test_nonphysical_input_is_rejected():
 
 
 @pytest.mark.parametrize("shape", [(250, 77), (61, 5), (7, 130), (1, 3)])
-@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1)])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
 def test_one_step_2d(shape, bc):
     nx, ny = shape
     w = rect_periodic(nx, ny, 23, bc)
@@ -86,6 +86,24 @@ def test_one_step_2d(shape, bc):
     out = g.step(dt).cpu().numpy()
     assert max_rel_error(out, ref) <= TOL1
     # fused CFL rate of the output
+    assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
+
+
+@pytest.mark.parametrize("rows", [1, 2, 3, 5])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (1, 0)])
+def test_one_step_2d_short_segments(rows, bc, monkeypatch):
+    """Row segments shorter than the march's two halo rows (the CSH_ROWS
+    override, read when a handle is created): every segment edge is a
+    boundary of the row rings."""
+    monkeypatch.setenv("CSH_ROWS", str(rows))
+    w = rect_periodic(127, 23, 25, bc)
+    say("one step 2d, rows per segment", rows, bc)
+    g = gpu_grid(w)
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    dt = 0.8 / oracle.max_signal_speed(og, U0)
+    ref = oracle.step(og, dt, U0)
+    assert max_rel_error(g.step(dt).cpu().numpy(), ref) <= TOL1
     assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
 
 
