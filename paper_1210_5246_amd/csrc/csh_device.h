@@ -478,16 +478,18 @@ CSH_HD Cons<T> kt_flux2_x(const Prim<T>& wl, const Prim<T>& wr)
 // External flat-rotation-curve potential (Sec. 3.3, last paragraph): exact
 // kick of the velocity by dt * a for a fixed field a (rho and the stress
 // unchanged): rho u_i += dt rho a_i, E_ij += dt (a_i m_j + m_i a_j) + dt^2 rho a_i a_j.
-// P carries vc2 (0: no field), rc2, x0, y0, dx, dy of the grid.
+// P carries vc2 (0: no field), rc2, x0, y0, dx, dy of the grid.  Evaluated
+// in the state's precision (an FP32 state's kick in FP32: its rounding is that
+// of the state it updates).
 template <typename T, typename P>
 __device__ __forceinline__ void kick(Cons<T>& U, const P& p, double dt, int i, int j, bool twod)
 {
     if (p.vc2 == 0.0) return;
-    const double x = p.x0 + (i + 0.5) * p.dx;
-    const double y = twod ? p.y0 + (j + 0.5) * p.dy : 0.0;
+    const T x = T(p.x0) + (T(i) + T(0.5)) * T(p.dx);
+    const T y = twod ? T(p.y0) + (T(j) + T(0.5)) * T(p.dy) : T(0);
     // velocity increment g = dt a, a = -vc2 (x, y) / (x^2 + y^2 + rc^2)
-    const double f = (-p.vc2 * dt) * rcp(x * x + y * y + p.rc2);
-    const T gx = T(f * x), gy = T(f * y);
+    const T f = T(-p.vc2 * dt) * rcp(x * x + y * y + T(p.rc2));
+    const T gx = f * x, gy = f * y;
     // m' = m + rho g; E' = E + g_i m_j + m_i g_j + rho g_i g_j, i.e.
     // E'_xx = E_xx + g_x (m_x + m'_x), E'_xy = E_xy + g_x m_y + g_y m'_x
     const T mx = U.mx + U.r * gx, my = U.my + U.r * gy;
@@ -499,18 +501,20 @@ __device__ __forceinline__ void kick(Cons<T>& U, const P& p, double dt, int i, i
 }
 
 // CFL rate of a cell (the timestep is C / max over cells of this):
-// (|u| + a_x)/dx + (|v| + a_y)/dy, 1-D: (|u| + a_x)/dx.
+// (|u| + a_x)/dx + (|v| + a_y)/dy, 1-D: (|u| + a_x)/dx.  Evaluated in the
+// state's precision (FP32 for an FP32 state: a relative rounding of ~1e-7 in
+// a quantity that only sets the timestep) and returned as a double.
 template <typename T, bool TWOD>
 CSH_HD double signal_rate(const Prim<T>& w, double idx, double idy)
 {
-    const double ir = rcp(double(w.r));
-    const double tx = 3.0 * double(w.pxx) * ir;
-    double s = (fabs(double(w.u)) + tx * rsqrt(tx)) * idx;
+    const T ir = rcp(w.r);
+    const T tx = T(3) * w.pxx * ir;
+    T s = (fabs(w.u) + tx * rsqrt(tx)) * T(idx);
     if (TWOD) {
-        const double ty = 3.0 * double(w.pyy) * ir;
-        s += (fabs(double(w.v)) + ty * rsqrt(ty)) * idy;
+        const T ty = T(3) * w.pyy * ir;
+        s += (fabs(w.v) + ty * rsqrt(ty)) * T(idy);
     }
-    return s;
+    return double(s);
 }
 
 // CFL rate of a new 2-D state together with the test of physical() (rho > 0,
