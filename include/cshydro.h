@@ -22,6 +22,14 @@
  *     returns a message for the calling thread's last error.  No C++ exception
  *     crosses this interface.
  *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Launch shape: each 2-D and 3-D sweep kernel marches a wavefront over a
+ *     segment of rows (planes in 3-D) whose length the library chooses from
+ *     the grid size.  Three environment variables, for tuning only, set that
+ *     length instead (a positive integer; anything else is ignored); results
+ *     agree to rounding for any length:
+ *       CSH_ROWS     the characteristic sweeps, read when a 2-D handle is created;
+ *       CSH_KT_ROWS  the Kurganov-Tadmor step, read at every 2-D launch;
+ *       CSH_PLANES   the 3-D sweep, read at every step.
  */
 #ifndef CSHYDRO_H
 #define CSHYDRO_H

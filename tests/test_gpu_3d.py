@@ -67,14 +67,22 @@ def test_3d_one_step(n, bc):
 def test_3d_short_segments(planes, bc, monkeypatch):
     """z segments shorter than the march's halo planes (the CSH_PLANES
     override, read at each launch)."""
-    monkeypatch.setenv("CSH_PLANES", str(planes))
     W, g, h = workload((37, 11, 13), 73, bc)
     say("3d one step, planes per segment", planes, bc)
     G = gpu(W, h, bc)
     U0 = oracle.cons3_field(W)
     dt = 0.8 / oracle.max_signal_speed3(g, U0)
+    default = G.step(dt).cpu().numpy()  # the library's own segment length
+    monkeypatch.setenv("CSH_PLANES", str(planes))
+    out = G.step(dt).cpu().numpy()
     ref = oracle.step3(g, dt, U0)
-    assert rel_err(G.step(dt).cpu().numpy(), ref) <= 1e-12
+    assert rel_err(out, ref) <= 1e-12
+    # the same arithmetic per cell; which unrolled copy of the march loop takes a
+    # row depends on where its segment starts, and the compiler may fuse the
+    # multiply-adds of the copies differently: equal to rounding
+    dev = rel_err(out, default)
+    say("difference from the default segment length:", dev)
+    assert dev <= 1e-14
     assert G.last_signal_speed() == pytest.approx(oracle.max_signal_speed3(g, ref), rel=1e-13)
 
 

@@ -75,15 +75,23 @@ def test_kt_short_segments(rows, bc, monkeypatch):
     """Row segments shorter than the fused march's halo (stage 1 runs 4 rows
     ahead of stage 2's owned rows; the CSH_KT_ROWS override, read at each
     launch): the ghost-row copies and the ring slots at every segment edge."""
-    monkeypatch.setenv("CSH_KT_ROWS", str(rows))
     w = rect_periodic(127, 23, 43, bc)
     say("kt one step, rows per segment", rows, bc)
     g = kt_grid(w)
     og = ogrid(w)
     U0 = oracle.cons_field(w.W)
     dt = 0.8 / oracle.max_signal_speed(og, U0)
+    default = g.step(dt).cpu().numpy()  # the library's own segment length
+    monkeypatch.setenv("CSH_KT_ROWS", str(rows))
+    out = g.step(dt).cpu().numpy()
     ref = oracle.step_kt(og, dt, U0)
-    assert max_rel_error(g.step(dt).cpu().numpy(), ref) <= TOL1
+    assert max_rel_error(out, ref) <= TOL1
+    # the same arithmetic per cell; which unrolled copy of the march loop takes a
+    # row depends on where its segment starts, and the compiler may fuse the
+    # multiply-adds of the copies differently: equal to rounding
+    dev = max_rel_error(out, default)
+    say("difference from the default segment length:", dev)
+    assert dev <= 1e-14
     assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
 
 

@@ -95,15 +95,23 @@ def test_one_step_2d_short_segments(rows, bc, monkeypatch):
     """Row segments shorter than the march's two halo rows (the CSH_ROWS
     override, read when a handle is created): every segment edge is a
     boundary of the row rings."""
-    monkeypatch.setenv("CSH_ROWS", str(rows))
     w = rect_periodic(127, 23, 25, bc)
     say("one step 2d, rows per segment", rows, bc)
-    g = gpu_grid(w)
     og = ogrid(w)
     U0 = oracle.cons_field(w.W)
     dt = 0.8 / oracle.max_signal_speed(og, U0)
+    default = gpu_grid(w).step(dt).cpu().numpy()  # the library's own segment length
+    monkeypatch.setenv("CSH_ROWS", str(rows))
+    g = gpu_grid(w)
+    out = g.step(dt).cpu().numpy()
     ref = oracle.step(og, dt, U0)
-    assert max_rel_error(g.step(dt).cpu().numpy(), ref) <= TOL1
+    assert max_rel_error(out, ref) <= TOL1
+    # the same arithmetic per cell; which unrolled copy of the march loop takes a
+    # row depends on where its segment starts, and the compiler may fuse the
+    # multiply-adds of the copies differently: equal to rounding
+    dev = max_rel_error(out, default)
+    say("difference from the default segment length:", dev)
+    assert dev <= 1e-14
     assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
 
 
