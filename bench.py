@@ -112,6 +112,18 @@ def time_kernel(g, U0, steps, dt):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, max_seconds=20.0):
     """The CPU oracle on a bounded sample of the same workload: whole-grid
     steps of the 4096^2 disc until ~max_seconds of work (at least one)."""
@@ -129,7 +141,7 @@ def cpu_baseline(w, max_seconds=20.0):
             break
     threads = oracle.num_threads()
     return {"value": steps * w.nx * w.ny / el, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{steps} whole-grid step(s) of the {w.nx}x{w.ny} disc (same input), "
                       f"{el:.1f} s, FP64 C oracle with {threads} OpenMP threads"}
 
@@ -414,7 +426,10 @@ def main():
                      "kernel_source_hash": sweep_source_hash(),
                      "algorithmic_bytes_per_launch": f64["bpc"] * cells,
                      "valu": valu_summary(counters, f64["kernel_s"], cells),
-                     "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs},
+                     "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs,
+                     # measured HBM bytes (the counters' traffic) per second of kernel time
+                     "traffic_GBs": (counters["bytes_per_launch"] / f64["kernel_s"] / 1e9
+                                     if counters.get("bytes_per_launch") else None)},
     }
     if "f32" in res:
         f32 = res["f32"]

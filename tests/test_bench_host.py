@@ -42,3 +42,8 @@ def test_valu_summary_arithmetic():
     assert v["issue_tlane_instr_per_s"] == pytest.approx(0.5)
     assert v["issue_peak_tlane_instr_per_s"] == pytest.approx(256 * 4 * 16 * 2.4e9 / 1e12)
     assert bench.valu_summary({}, 1e-6, cells) is None
+
+
+def test_cpu_model_is_a_name():
+    name = bench.cpu_model()
+    assert isinstance(name, str) and name
