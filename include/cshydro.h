@@ -205,8 +205,8 @@ int csh_run_dts(csh_grid *h, int nsteps, const double *dts, void *U, void *U_wor
  * argument), external kick included.  U, lam_next: device, read only;
  * lam: device output; all [6][ny][nx] of the handle's dtype (CSH_F64 only).
  * Does not touch the handle's CFL state.  The first call allocates a workspace
- * of 78 (nx + 2)(ny + 2) doubles (1-D: 78 (nx + 2)) that the handle keeps
- * until csh_destroy.  Asynchronous.
+ * of 66 (nx + 2)(ny + 2) + 6 (nx + 4)(ny + 2) doubles (1-D: 66 (nx + 2) +
+ * 6 (nx + 4)) that the handle keeps until csh_destroy.  Asynchronous.
  */
 int csh_adjoint_step(csh_grid *h, double dt, const void *U, const void *lam_next, void *lam);
 

@@ -436,11 +436,13 @@ struct AdjArgs {
     double* lam0;        // lam^n
     double* FS;          // [4 faces][6][ext]
     double* FSb;         // [4][6][ext]
-    double* Cs;          // [5 roles][6][ext]
+    double* Cs;          // [3 roles][6][ext]: the y part's shares (SELF, DOWN, UP)
+    double* XS;          // [6][ey][nx + 4]: per padded position (column -2 .. nx + 1 of an extended
+                         // row), SELF and the x part's shares summed
 };
 
 enum { XHI = 0, XLO = 1, YHI = 2, YLO = 3 };
-enum { SELF = 0, LEFT = 1, RIGHT = 2, DOWN = 3, UP = 4 };
+enum { SELF = 0, DOWN = 1, UP = 2 };
 
 CSH_HD P load_p(const double* B, size_t plane, size_t slot, size_t idx)
 {
@@ -570,29 +572,24 @@ CSH_HD void cells_cell_y(const AdjArgs& a, int i, int j)
     store_p(a.Cs, ne, UP, e, bp);
 }
 
-// x part: adds to SELF (2-D: after the y part), writes LEFT, RIGHT
+// x part of extended cell (i, j): b0 = its SELF share (2-D: the y part's plus
+// this part's), bl, br its LEFT and RIGHT shares (to positions i - 1, i + 1)
 template <bool TWOD>
-CSH_HD void cells_cell_x(const AdjArgs& a, int i, int j)
+CSH_HD void cells_x_vjp(const AdjArgs& a, int i, int j, P& b0, P& bl, P& br)
 {
     const double kx = a.dt / (2.0 * a.dx);
     const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
     const P W0 = prim_at(a, i, j, TWOD);
     const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
     const Faces<double> fb = load_face_adjoints(a, ne, e, TWOD);
-    P b0 = TWOD ? load_p(a.Cs, ne, SELF, e) : zero_p(), bl = zero_p(), br = zero_p();
+    b0 = TWOD ? load_p(a.Cs, ne, SELF, e) : zero_p();
+    bl = zero_p();
+    br = zero_p();
     face_states_vjp_x<TWOD>(W0, Wl, Wr, kx, fb, b0, bl, br);
-    store_p(a.Cs, ne, SELF, e, b0);
-    store_p(a.Cs, ne, LEFT, e, bl);
-    store_p(a.Cs, ne, RIGHT, e, br);
 }
 
-// both parts, in the order the GPU runs them (y kernel, then x kernel)
-template <bool TWOD>
-CSH_HD void cells_cell(const AdjArgs& a, int i, int j)
-{
-    if constexpr (TWOD) cells_cell_y(a, i, j);
-    cells_cell_x<TWOD>(a, i, j);
-}
+// index of padded position (px, j), px in [-2, nx + 1], j an extended row, in XS
+CSH_HD size_t xs_index(const AdjArgs& a, int px, int j) { return (size_t)(j + (a.ey > 1 ? 1 : 0)) * (a.nx + 4) + (px + 2); }
 
 // positions p in [-2, n+1] (the ghost-padded range the stencil reads) with
 // map(p) == i; returns their count (at most 5)
@@ -611,16 +608,16 @@ CSH_HD int preimages(int i, int n, int bc, int* p)
     return k;
 }
 
-// sum of the slots that land on padded position (pi, pj)
+// sum of the shares that land on padded position (pi, pj): the x-part sum of
+// its row (extended rows only) and the y part's DOWN and UP shares of the
+// extended cells above and below
 template <bool TWOD>
 CSH_HD P pad_sum(const AdjArgs& a, int pi, int pj)
 {
-    const size_t ne = (size_t)a.ex * a.ey;
+    const size_t ne = (size_t)a.ex * a.ey, nxs = (size_t)(a.nx + 4) * a.ey;
     auto in_ext = [&](int i, int j) { return i >= -1 && i <= a.nx && (!TWOD || (j >= -1 && j <= a.ny)); };
     P s = zero_p();
-    if (in_ext(pi, pj)) acc(s, load_p(a.Cs, ne, SELF, ext_index(a, pi, pj)));
-    if (in_ext(pi + 1, pj)) acc(s, load_p(a.Cs, ne, LEFT, ext_index(a, pi + 1, pj)));
-    if (in_ext(pi - 1, pj)) acc(s, load_p(a.Cs, ne, RIGHT, ext_index(a, pi - 1, pj)));
+    if (!TWOD || (pj >= -1 && pj <= a.ny)) acc(s, load_p(a.XS, nxs, 0, xs_index(a, pi, pj)));
     if (TWOD) {
         if (in_ext(pi, pj + 1)) acc(s, load_p(a.Cs, ne, DOWN, ext_index(a, pi, pj + 1)));
         if (in_ext(pi, pj - 1)) acc(s, load_p(a.Cs, ne, UP, ext_index(a, pi, pj - 1)));

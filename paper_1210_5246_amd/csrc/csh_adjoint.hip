@@ -13,13 +13,17 @@
 //              dt/dx (lam'_{i+1} - lam'_i), HLL vjp -> adjoints of the two face
 //              states, each written to its one slot in FSb
 //   3. cells:  per extended cell, the vjp of its face-state computation gives
-//              the adjoints of its five input primitive states -> slots
-//              C[self, left, right, down, up]; in two kernels, the y part
-//              (self, down, up) and then the x part (adds to self; left,
-//              right), which halves the live state of each
-//   4. gather: per interior cell, sum the slots that land on each padded
-//              position, fold the padded positions that the boundary mapping
-//              sends to this cell, chain through W(U) and add lam' itself.
+//              the adjoints of its five input primitive states; in two
+//              kernels, which halves the live state of each: the y part ->
+//              slots C[self, down, up], then the x part (adds to self; left,
+//              right shares), whose wavefronts each cover 64 consecutive
+//              cells of a row and sum self + the right neighbour's left share
+//              + the left neighbour's right share by lane shifts into one
+//              value per padded position (XS) for the 62 inner lanes
+//   4. gather: per interior cell, sum XS and the down / up slots that land on
+//              each padded position, fold the padded positions that the
+//              boundary mapping sends to this cell, chain through W(U) and
+//              add lam' itself.
 //
 // The kernels take their workgroup numbers XCD-aware (xcd_block), so the rows
 // a thread reads from its y neighbours sit in the same L2.
@@ -47,7 +51,32 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a)
     if (STAGE == 1) faces_cell<TWOD>(a, i, j);
     if (STAGE == 2) hll_cell<TWOD>(a, i, j);
     if constexpr (STAGE == 3 && TWOD) cells_cell_y(a, i, j);
-    if (STAGE == 5) cells_cell_x<TWOD>(a, i, j);
+}
+
+// Stage 5, the x part, summed per padded position: a wavefront covers the
+// extended columns base .. base + 63 of one extended row (base = 62 w - 3) and
+// writes the padded positions of its lanes 1..62; lanes outside the extended
+// range contribute zero.  The summation order is that of a per-position sum of
+// slots: self, then the left share of the cell to the right, then the right
+// share of the cell to the left.
+constexpr int kXsOwned = 62;
+
+template <bool TWOD>
+__global__ __launch_bounds__(256) void adjoint_xsum_kernel(AdjArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const long w = (long)xcd_block(blockIdx.x, gridDim.x) * 4 + wave_in_block();
+    const int wpr = (a.nx + 4 + kXsOwned - 1) / kXsOwned;  // wavefronts per extended row
+    if (w >= (long)wpr * a.ey) return;                     // uniform per wavefront
+    const int j = TWOD ? (int)(w / wpr) - 1 : 0;
+    const int i = (int)(w % wpr) * kXsOwned - 3 + lane;
+    P b0 = zero_p(), bl = zero_p(), br = zero_p();
+    if (i >= -1 && i <= a.nx) cells_x_vjp<TWOD>(a, i, j, b0, bl, br);
+    const P l = lane_shift<+1>(bl), r = lane_shift<-1>(br);  // from the cells at i + 1, i - 1
+    const P sum = {b0.r + l.r + r.r,       b0.u + l.u + r.u,       b0.v + l.v + r.v,
+                   b0.pxx + l.pxx + r.pxx, b0.pxy + l.pxy + r.pxy, b0.pyy + l.pyy + r.pyy};
+    if (lane >= 1 && lane <= kXsOwned && i >= -2 && i <= a.nx + 1)
+        store_p(a.XS, (size_t)(a.nx + 4) * a.ey, 0, xs_index(a, i, j), sum);
 }
 
 __global__ __launch_bounds__(256) void init_adjoint_kernel(const double* W, const double* lamU, double* lamW, int64_t n)
@@ -69,8 +98,8 @@ __global__ __launch_bounds__(256) void init_adjoint_kernel(const double* W, cons
 
 size_t csh_adjoint_workspace_doubles(int nx, int ny)
 {
-    const size_t ne = (size_t)(nx + 2) * (ny > 1 ? ny + 2 : 1);
-    return ne * 6 * (4 + 4 + 5);
+    const size_t ey = ny > 1 ? ny + 2 : 1, ne = (size_t)(nx + 2) * ey;
+    return ne * 6 * (4 + 4 + 3) + (size_t)(nx + 4) * ey * 6;
 }
 
 int csh_adjoint_impl(csh_grid_view v, double dt, const void* U, const void* lam_next, void* lam, double* ws,
@@ -99,17 +128,20 @@ int csh_adjoint_impl(csh_grid_view v, double dt, const void* U, const void* lam_
     a.FS = ws;
     a.FSb = ws + 24 * ne;
     a.Cs = ws + 48 * ne;
+    a.XS = ws + 66 * ne;
     const unsigned be = (unsigned)((ne + 255) / 256), bi = (unsigned)(((size_t)v.nx * v.ny + 255) / 256);
+    const long xs_waves = (long)((a.nx + 4 + kXsOwned - 1) / kXsOwned) * a.ey;
+    const unsigned bx = (unsigned)((xs_waves + 3) / 4);
     if (twod) {
         adjoint_kernel<true, 1><<<be, 256, 0, s>>>(a);
         adjoint_kernel<true, 2><<<be, 256, 0, s>>>(a);
         adjoint_kernel<true, 3><<<be, 256, 0, s>>>(a);
-        adjoint_kernel<true, 5><<<be, 256, 0, s>>>(a);
+        adjoint_xsum_kernel<true><<<bx, 256, 0, s>>>(a);
         adjoint_kernel<true, 4><<<bi, 256, 0, s>>>(a);
     } else {
         adjoint_kernel<false, 1><<<be, 256, 0, s>>>(a);
         adjoint_kernel<false, 2><<<be, 256, 0, s>>>(a);
-        adjoint_kernel<false, 5><<<be, 256, 0, s>>>(a);
+        adjoint_xsum_kernel<false><<<bx, 256, 0, s>>>(a);
         adjoint_kernel<false, 4><<<bi, 256, 0, s>>>(a);
     }
     const hipError_t e = hipGetLastError();

@@ -39,8 +39,27 @@ static void adjoint_loops(AdjArgs& a)
         for (int i = -1; i <= a.nx; ++i) faces_cell<TWOD>(a, i, j);
     for (int j = j0; j <= j1; ++j)
         for (int i = -1; i <= a.nx; ++i) hll_cell<TWOD>(a, i, j);
+    if constexpr (TWOD)
+        for (int j = j0; j <= j1; ++j)
+            for (int i = -1; i <= a.nx; ++i) cells_cell_y(a, i, j);
+    // x part: self, left and right shares per extended cell, then one sum per
+    // padded position in the kernel's order (self, left share of the cell to
+    // the right, right share of the cell to the left; zero outside the range)
+    const size_t ne = (size_t)a.ex * a.ey, nxs = (size_t)(a.nx + 4) * a.ey;
+    std::vector<P> b0(ne, zero_p()), bl(ne, zero_p()), br(ne, zero_p());
     for (int j = j0; j <= j1; ++j)
-        for (int i = -1; i <= a.nx; ++i) cells_cell<TWOD>(a, i, j);
+        for (int i = -1; i <= a.nx; ++i) {
+            const size_t e = ext_index(a, i, j);
+            cells_x_vjp<TWOD>(a, i, j, b0[e], bl[e], br[e]);
+        }
+    auto share = [&](const std::vector<P>& v, int i, int j) { return i >= -1 && i <= a.nx ? v[ext_index(a, i, j)] : zero_p(); };
+    for (int j = j0; j <= j1; ++j)
+        for (int px = -2; px <= a.nx + 1; ++px) {
+            const P s0 = share(b0, px, j), l = share(bl, px + 1, j), r = share(br, px - 1, j);
+            const P sum = {s0.r + l.r + r.r,       s0.u + l.u + r.u,       s0.v + l.v + r.v,
+                           s0.pxx + l.pxx + r.pxx, s0.pxy + l.pxy + r.pxy, s0.pyy + l.pyy + r.pyy};
+            store_p(a.XS, nxs, 0, xs_index(a, px, j), sum);
+        }
     for (int j = 0; j < (TWOD ? a.ny : 1); ++j)
         for (int i = 0; i < a.nx; ++i) gather_cell<TWOD>(a, i, j);
 }
@@ -51,10 +70,11 @@ extern "C" int host_adjoint_step(int nx, int ny, int bcx, int bcy, double dx, do
     AdjArgs a = make_args(nx, ny, bcx, bcy, dx, dy, dt, vc, rc, x0, y0, U);
     const size_t ne = (size_t)a.ex * a.ey;
     // NaN-filled: every slot the reverse pass reads must have been written by it
-    std::vector<double> ws(78 * ne, std::numeric_limits<double>::quiet_NaN());
+    std::vector<double> ws(66 * ne + 6 * (size_t)(nx + 4) * a.ey, std::numeric_limits<double>::quiet_NaN());
     a.FS = ws.data();
     a.FSb = ws.data() + 24 * ne;
     a.Cs = ws.data() + 48 * ne;
+    a.XS = ws.data() + 66 * ne;
     a.lam1 = lam1;
     a.lam0 = lam0;
     if (ny > 1) adjoint_loops<true>(a);
