@@ -25,13 +25,14 @@ def say(*a):
 
 
 def small_case(kind, bc, n):
+    m = max(64, n + 24)  # the generator's width (64 for the sizes up to 40)
     if kind == "2d":
-        w = wl.periodic(64, 61)
+        w = wl.periodic(m, 61)
         W = np.ascontiguousarray(w.W[:, 10:10 + n, 20:20 + n])
         W[1:3] *= 2.0
         g = oracle.Grid(n, n, 1.0 / n, 1.2 / n, bc, bc, -0.4, -0.55, 0.8 if bc else 0.0, 0.1)
     else:
-        w = wl.periodic(64, 62)
+        w = wl.periodic(m, 62)
         W = np.ascontiguousarray(w.W[:, 9, 3:3 + n])
         W[1] *= 2.0
         g = oracle.Grid(n, 1, 1.0 / n, 1.0, bc, bc, -0.3, 0.0, 0.6 if bc else 0.0, 0.2)
@@ -69,12 +70,15 @@ def test_gpu_adjoint_matches_oracle_dense_jacobian(kind, bc):
     assert dev.max() < 1e-6, dev.max()
 
 
-@pytest.mark.parametrize("kind", ["1d", "2d"])
+# sizes around the x-part kernel's wavefronts (62 padded positions each, nx + 4
+# per row: one wavefront at 58, two at 59 and 120, three at 121) and tiny grids
+@pytest.mark.parametrize("kind,n", [("1d", m) for m in (1, 2, 3, 37, 58, 59, 121)] +
+                         [("2d", m) for m in (2, 3, 37, 58, 59, 121)])
 @pytest.mark.parametrize("bc", [0, 1])
-def test_gpu_adjoint_matches_host_reverse_pass(kind, bc):
+def test_gpu_adjoint_matches_host_reverse_pass(kind, n, bc):
     import test_adjoint_host as th
-    W, g = small_case(kind, bc, 37)
-    say("adjoint gpu vs host", kind, bc)
+    W, g = small_case(kind, bc, n)
+    say("adjoint gpu vs host", kind, n, bc)
     U = oracle.cons_field(W)
     dt = 0.8 / oracle.max_signal_speed(g, U)
     lam = np.random.default_rng(5).standard_normal(U.shape)
