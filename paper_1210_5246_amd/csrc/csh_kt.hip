@@ -100,8 +100,8 @@ __global__ __launch_bounds__(64 * kWaves) void kt_kernel(StepArgs<T> p)
 // the 240 B of two launches.  A wavefront owns 56 columns: stage 1 is valid on
 // lanes 2..61, stage 2 on lanes 4..59.
 //
-// Boundaries.  Stage 2 of the two-launch form reads U* through the boundary
-// map, i.e. at a ghost position it sees U* of the mapped cell.  With periodic
+// Boundaries.  The boundary conditions apply to U* as to any state: at a
+// ghost position stage 2 sees U* of the mapped cell.  With periodic
 // boundaries the lanes and rows of a wavefront hold a contiguous window of
 // the torus, so its own U* at a ghost position is already that value; with
 // outflow boundaries the ghost columns take U* of the edge column by a lane
