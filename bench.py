@@ -212,9 +212,9 @@ def bench_adjoint(n=512, steps=200, K=20, ndirs=64):
     rho_t = Gt.U[0].clone()
     Wd = torch.from_numpy(w0.W).to("cuda")
 
-    def grad_once():
+    def grad_once(k=K):
         W0 = Wd.clone().requires_grad_(True)
-        U, dts = cag.sweep(W0, w0.dx, w0.dy, nsteps=steps, checkpoint_every=K)
+        U, dts = cag.sweep(W0, w0.dx, w0.dy, nsteps=steps, checkpoint_every=k)
         L = 0.5 * ((U[0] - rho_t) ** 2).sum()
         (gr,) = torch.autograd.grad(L, W0)
         return gr, dts
@@ -225,6 +225,16 @@ def bench_adjoint(n=512, steps=200, K=20, ndirs=64):
     gr, dts = grad_once()
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
+    # the same gradient with every state kept (checkpoint_every=1: one launch
+    # sequence writes the trajectory, nothing is recomputed); bitwise equal
+    grad_once(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr1, _ = grad_once(1)
+    torch.cuda.synchronize()
+    t_grad_all = time.perf_counter() - t0
+    same_all = bool(torch.equal(gr1, gr))
+    del gr1
     g = csh.Grid(Wd, w0.dx, w0.dy)
     U0 = g.U.clone()
     g.run_cfl(steps, 0.8)
@@ -255,6 +265,7 @@ def bench_adjoint(n=512, steps=200, K=20, ndirs=64):
     return {"workload": f"periodic {n}x{n} FP64, {steps} steps, checkpoints every {K}, "
                         f"gradient vs central differences on {ndirs} directions (eps {eps})",
             "adjoint_gradient_s": t_grad, "forward_s": t_fwd, "fd_gradient_s": t_fd,
+            "adjoint_gradient_s_all_states": t_grad_all, "all_states_gradient_bitwise_equal": same_all,
             "speedup": t_fd / t_grad, "adjoint_over_forward": t_grad / t_fwd,
             "max_fd_deviation_over_sum_abs_terms_eps1e-6": worst}
 

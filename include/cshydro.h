@@ -189,6 +189,19 @@ int csh_run_cfl(csh_grid *h, int nsteps, double cfl, double t_end, void *U, void
                 double *dt_log);
 
 /*
+ * nsteps steps as csh_run_cfl (t_end none), keeping every state: states is a
+ * caller-owned device array [nsteps][6][ny][nx] of the handle's dtype (nsteps
+ * times the state size), and states[k] receives the state after step k + 1;
+ * the first step reads U0 (device, read only, not inside states).  dt_log:
+ * as for csh_run_cfl.  The states are bitwise those csh_run_cfl passes
+ * through.  For reverse passes that keep the whole trajectory in memory (a
+ * 512 x 512 FP64 run of 200 steps is 2.5 GB).  The steps are launched on the
+ * handle's stream directly (no graph: the state array is usually new at every
+ * call); asynchronous.
+ */
+int csh_run_cfl_states(csh_grid *h, int nsteps, double cfl, const void *U0, void *states, double *dt_log);
+
+/*
  * Advance nsteps steps with given timesteps: step k uses dts[k] (device array
  * of nsteps doubles, read when the step runs).  U is updated in place (U_work
  * as for csh_run_cfl); captured once as a HIP graph per (nsteps, buffers, dts)

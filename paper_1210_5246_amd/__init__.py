@@ -66,6 +66,7 @@ _SIGNATURES = [
     ("csh_last_signal_speed", ctypes.c_int, [_vp, _dp]),
     ("csh_fluxes", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _vp]),
     ("csh_run_cfl", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]),
+    ("csh_run_cfl_states", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp]),
     ("csh_run_dts", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     ("csh_adjoint_step", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp, _vp]),
     ("csh_init_state_adjoint", ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -221,6 +222,21 @@ class Grid:
         _check(lib().csh_run_cfl(self._h, int(nsteps), float(cfl), float(t_end), _dev(U, self.dtype, self.n),
                                  _dev(work, self.dtype, self.n), _dev(dt_log, torch.float64, nsteps, True)))
         return dt_log[:nsteps]
+
+    def run_cfl_states(self, nsteps: int, cfl: float = 0.8, U0: torch.Tensor | None = None,
+                       states: torch.Tensor | None = None, dt_log: torch.Tensor | None = None):
+        """``nsteps`` device-timed CFL steps from ``U0`` (default ``self.U``, left
+        unchanged) keeping every state; returns (states [nsteps, *U0.shape],
+        per-step timesteps as a GPU float64 tensor)."""
+        U0 = self.U if U0 is None else U0
+        if states is None:
+            states = torch.empty((max(nsteps, 1),) + tuple(U0.shape), dtype=U0.dtype, device=U0.device)
+        if dt_log is None:
+            dt_log = torch.empty(max(nsteps, 1), dtype=torch.float64, device=U0.device)
+        _check(lib().csh_run_cfl_states(self._h, int(nsteps), float(cfl), _dev(U0, self.dtype, self.n),
+                                        _dev(states, self.dtype, nsteps * self.n, True),
+                                        _dev(dt_log, torch.float64, nsteps, True)))
+        return states[:nsteps], dt_log[:nsteps]
 
     def run_dts(self, dts: torch.Tensor, U: torch.Tensor | None = None, work: torch.Tensor | None = None):
         """Advance ``U`` (default ``self.U``) in place with the timesteps ``dts`` (GPU float64)."""

@@ -3,7 +3,9 @@ HIP sweep, with the hand-written adjoint (``csh_adjoint_step``) in backward.
 
 Forward: primitive fields W0 -> conserved U0 (``csh_init_state``), then
 ``nsteps`` steps with the CFL timestep chosen on the device (``csh_run_cfl``),
-keeping the state every ``checkpoint_every`` steps and the timesteps taken.
+keeping the state every ``checkpoint_every`` steps and the timesteps taken;
+with ``checkpoint_every=1`` one ``csh_run_cfl_states`` launch keeps every
+state (nsteps states in device memory, no recomputation in backward).
 Backward: the timesteps are frozen (the gradient is that of the map with the
 recorded dt list); segment by segment from the last, the states of the segment
 are recomputed from its checkpoint with those timesteps (``csh_step``) and the
@@ -68,7 +70,15 @@ class AdjointSweep(torch.autograd.Function):
             assert len(dts) == nsteps
         else:
             dts_dev = torch.empty(max(nsteps, 1), dtype=torch.float64, device=U.device)
-        done = 0
+        if K == 1 and dts is None and nsteps > 0:
+            # every state kept (nsteps states in device memory): one graph launch
+            # writes the whole trajectory and the reverse pass recomputes nothing
+            states, _ = g.run_cfl_states(nsteps, cfl, U0=U, dt_log=dts_dev)
+            ckpts = [U.clone()] + [states[k] for k in range(nsteps - 1)]
+            U = states[nsteps - 1]
+            done = nsteps
+        else:
+            done = 0
         while done < nsteps:
             k = min(K, nsteps - done)
             ckpts.append(U.clone())

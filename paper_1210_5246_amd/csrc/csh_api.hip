@@ -368,7 +368,27 @@ hipError_t enqueue_run(csh_grid* h, int nsteps, double cfl, double t_end, void* 
     return e;
 }
 
+// nsteps CFL steps keeping every state: step k reads the previous step's
+// output (U0 for the first) and writes slot k of states
+hipError_t enqueue_run_states(csh_grid* h, int nsteps, double cfl, const void* U0, void* states, double* dt_log,
+                              hipStream_t s)
+{
+    h->phase = 0;
+    hipError_t e = enqueue_maxspeed(h, U0, s);  // rate of the initial state into slot 0, t = 0
+    const size_t bytes = 6 * (size_t)h->nx * h->ny * (h->dtype == CSH_F64 ? sizeof(double) : sizeof(float));
+    char* base = static_cast<char*>(states);
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+        const void* in = k == 0 ? U0 : base + (size_t)(k - 1) * bytes;
+        void* outp = base + (size_t)k * bytes;
+        double* lg = dt_log ? dt_log + k : nullptr;
+        e = h->dtype == CSH_F64 ? enqueue_step<double>(h, in, outp, 1, 0, cfl, 0.0, lg, s)
+                                : enqueue_step<float>(h, in, outp, 1, 0, cfl, 0.0, lg, s);
+    }
+    return e;
+}
+
 // record (once per distinct argument set) and replay the graph of a run
+// (mode 0: csh_run_cfl, 1: csh_run_dts)
 int run_graph(csh_grid* h, int mode, int nsteps, double cfl, double t_end, void* U, void* U_work,
               const void* lg)
 {
@@ -414,6 +434,20 @@ extern "C" int csh_run_cfl(csh_grid* h, int nsteps, double cfl, double t_end, vo
     if (nsteps < 0 || !(cfl > 0)) return csh_fail(CSH_ERR_ARG, "nsteps >= 0 and cfl > 0 required");
     if (nsteps == 0) return CSH_OK;
     return run_graph(h, 0, nsteps, cfl, t_end, U, U_work, dt_log);
+}
+
+extern "C" int csh_run_cfl_states(csh_grid* h, int nsteps, double cfl, const void* U0, void* states,
+                                  double* dt_log)
+{
+    if (!h || !U0 || !states) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (U0 == states) return csh_fail(CSH_ERR_ARG, "U0 must not be the state array");
+    if (nsteps < 0 || !(cfl > 0)) return csh_fail(CSH_ERR_ARG, "nsteps >= 0 and cfl > 0 required");
+    if (nsteps == 0) return CSH_OK;
+    // enqueued directly: the state array is usually new at every call, and at
+    // the sizes these runs serve a graph replay is no faster than the launches
+    const hipError_t e = enqueue_run_states(h, nsteps, cfl, U0, states, dt_log, h->stream);
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("run_cfl_states: ") + hipGetErrorString(e));
+    return CSH_OK;
 }
 
 extern "C" int csh_run_dts(csh_grid* h, int nsteps, const double* dts, void* U, void* U_work)

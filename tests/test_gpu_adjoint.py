@@ -125,7 +125,8 @@ def test_gradient_512_against_finite_differences():
     1/2 sum (rho_200 - rho*)^2 with respect to the initial primitive fields
     against central differences on 64 smooth directions: |fd - <grad, d>| <=
     1e-5 sum |grad * d| for every direction and <= 1e-5 |<grad, d>| for at
-    least 60 of them; checkpointed and stored-everything gradients bitwise equal."""
+    least 60 of them; gradients with checkpoints every 20 steps, one checkpoint
+    (everything recomputed) and every state kept bitwise equal."""
     w0, wt = wl.adjoint(512, 5, 6, 200, 20)
     say("target run")
     Gt = csh.Grid(torch.from_numpy(wt.W).to(DEV), wt.dx, wt.dy)
@@ -141,6 +142,11 @@ def test_gradient_512_against_finite_differences():
     U2, dts2 = cag.sweep(W0b, w0.dx, w0.dy, nsteps=200, checkpoint_every=200)
     (grad2,) = torch.autograd.grad(loss_of(U2, rho_t), W0b)
     assert torch.equal(dts, dts2) and torch.equal(grad, grad2)
+    say("forward + adjoint, K=1 (every state kept, no recomputation)")
+    W0c = torch.from_numpy(w0.W).to(DEV).requires_grad_(True)
+    U3, dts3 = cag.sweep(W0c, w0.dx, w0.dy, nsteps=200, checkpoint_every=1)
+    (grad3,) = torch.autograd.grad(loss_of(U3, rho_t), W0c)
+    assert torch.equal(dts, dts3) and torch.equal(U, U3) and torch.equal(grad, grad3)
     dirs = wl.fd_directions(512, 64)
     worst_scaled, plain_ok = 0.0, 0
     Wd = torch.from_numpy(w0.W).to(DEV)

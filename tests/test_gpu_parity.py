@@ -254,6 +254,30 @@ def test_fp32_twin_close_to_fp64():
     assert err < 1e-3
 
 
+@pytest.mark.parametrize("scheme,shape", [("muscl", (130, 70)), ("kt", (130, 70)), ("kt", (300, 1)), ("hllc", (61, 5))])
+def test_run_cfl_states_keeps_the_states_of_run_cfl(scheme, shape):
+    """csh_run_cfl_states: every kept state and timestep is bitwise the one
+    csh_run_cfl reaches after that many steps (disc-like potential on)."""
+    nx, ny = shape
+    w = rect_periodic(nx, max(ny, 2), 29, (1, 1))
+    if ny == 1:
+        w.W = np.ascontiguousarray(w.W[:, 0, :])
+        w.ny, w.dy = 1, 1.0
+    w.vc, w.rc, w.x0, w.y0 = 0.7, 0.1, -0.45, -0.5
+    say("run_cfl_states", scheme, shape)
+    g = gpu_grid(w)
+    g.set_scheme(scheme)
+    U0 = g.U.clone()
+    states, dts = g.run_cfl_states(7, 0.8)
+    assert torch.equal(g.U, U0)  # the initial state is only read
+    for k in (0, 3, 6):
+        r = gpu_grid(w)
+        r.set_scheme(scheme)
+        d = r.run_cfl(k + 1, 0.8)
+        assert torch.equal(states[k], r.U), k
+        assert torch.equal(dts[:k + 1], d), k
+
+
 def test_run_dts_replays_run_cfl_bitwise_and_set_state():
     w = wl.periodic(200, 27, 9)
     say("run_dts replay")
