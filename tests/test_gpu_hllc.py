@@ -2,7 +2,7 @@
 oracle's (reading H1), to the bars of the HLL sweep: max relative error
 (per-field metric of tests/parity.py) <= 1e-12 after one step and <= 1e-10
 after 100 steps, faces to 1e-13 of each field's scale, the full-size disc on
-sampled cells.  HLLC picks a side of the contact by the sign of S*; the flux is
+sampled cells and on every cell.  HLLC picks a side of the contact by the sign of S*; the flux is
 continuous there, so a different pick on a rounding-level S* costs rounding."""
 import sys
 
@@ -167,6 +167,19 @@ def test_hllc_disc_4096_one_step_sampled():
     cells = np.array(sorted(cells), dtype=np.int64)
     ref = oracle.step_cells(og, dt, U0, cells, "hllc").T
     assert max_rel_error(out[:, cells], ref) <= TOL1
+
+
+def test_hllc_disc_4096_one_step_full():
+    """Full-size disc (4096^2, FP64, outflow, potential): one HLLC step in the
+    launch configuration of the benchmark against the oracle on every cell."""
+    w = wl.disc(4096, 3, 1)
+    say("hllc disc 4096^2 one step, every cell (oracle ~5 s)")
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    g = hllc_grid(w)
+    dt = 0.8 / g.max_signal_speed()
+    out = g.step(dt).cpu().numpy()
+    assert max_rel_error(out, oracle.step(og, dt, U0, "hllc")) <= TOL1
 
 
 def test_hllc_fp32_and_adjoint_refusal():
