@@ -122,6 +122,9 @@ def lib():
         L.orc_max_signal_speed.argtypes = [G, _D]
         L.orc_max_signal_speed.restype = ctypes.c_double
         L.orc_physical.argtypes = [G, _D]
+        L.orc_branch_count.argtypes = [G]
+        L.orc_branch_count.restype = ctypes.c_int64
+        L.orc_branches.argtypes = [G, ctypes.c_double, _D, ctypes.POINTER(ctypes.c_int)]
         L.orc_cons_field.argtypes = [ctypes.c_int64, _D, _D]
         L.orc_prim_field.argtypes = [ctypes.c_int64, _D, _D]
         for name in ("orc_cons", "orc_prim", "orc_flux_x", "orc_flux_y"):
@@ -136,6 +139,7 @@ def lib():
         L.orc_trace.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, _D, _D]
         L.orc_hll.argtypes = [ctypes.c_int, _D, _D, _D]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_kt_flux.argtypes = [ctypes.c_int, _D, _D, _D]
         L.orc_step_kt.argtypes = [G, ctypes.c_double, _D, _D]
         L.orc_hllc.argtypes = [ctypes.c_int, _D, _D, _D]
@@ -244,6 +248,11 @@ SOLVERS = {"hll": 0, "hllc": 1}
 def num_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Set the OpenMP threads of the oracle's loops (the CPU baseline's 1-thread leg)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ---- fields ----------------------------------------------------------------------------
@@ -443,6 +452,40 @@ def max_signal_speed(g: Grid, U: np.ndarray) -> float:
 def physical(g: Grid, U: np.ndarray) -> bool:
     U = _check(g, U)
     return bool(lib().orc_physical(ctypes.byref(g.c()), _p(U)))
+
+
+MC_OFF, MC_CENTRED, MC_LEFT, MC_RIGHT = 0, 1, 2, 3
+
+
+def branches(g: Grid, dt: float, U: np.ndarray) -> dict:
+    """Branch pattern of one step (``orc_branches``): the side of every kink
+    of the scheme that each decision takes.
+
+    ``cells``: [ey, ex, 16] over the extended cells (j = -1..ny in 2-D, i =
+    -1..nx): per direction x then y, the limiter code of each of the six waves
+    (MC_OFF at an extremum, else MC_CENTRED / MC_LEFT / MC_RIGHT for the first
+    minimal argument of |dc|, 2|dl|, 2|dr|) and the tracing kinks
+    (lamM > 0, lam0 < 0); ``fx``: [ny, nx+1, 4] per x face i-1/2 and ``fy``
+    [ny+1, nx, 4] per y face (2-D): which face state sets S_L, S_L >= 0, which
+    sets S_R, S_R <= 0.
+    """
+    U = _check(g, U)
+    n = int(lib().orc_branch_count(ctypes.byref(g.c())))
+    codes = np.zeros(n, dtype=np.intc)
+    if lib().orc_branches(ctypes.byref(g.c()), dt, _p(U), codes.ctypes.data_as(ctypes.POINTER(ctypes.c_int))) != 0:
+        raise ValueError("bad grid")
+    twod = g.ny > 1
+    ex, ey = g.nx + 2, (g.ny + 2 if twod else 1)
+    nc = 16 * ex * ey
+    nfx = 4 * (g.nx + 1) * g.ny
+    out = {"cells": codes[:nc].reshape(ey, ex, 16), "fx": codes[nc:nc + nfx].reshape(g.ny, g.nx + 1, 4)}
+    if twod:
+        out["fy"] = codes[nc + nfx:].reshape(g.ny + 1, g.nx, 4)
+    return out
+
+
+def same_branches(a: dict, b: dict) -> bool:
+    return all(np.array_equal(a[k], b[k]) for k in a)
 
 
 # ---- drivers ---------------------------------------------------------------------------

@@ -263,12 +263,24 @@ static void matvec(const double M[NV][NV], const double x[NV], double y[NV])
     }
 }
 
+/* Which argument of eq. (25) the MC limiter takes (branch codes of
+ * orc_branches): 0 at an extremum (the TVD clause, reading R3), else the
+ * first minimal one of |dc| (1), 2|dl| (2), 2|dr| (3). */
+static int mc_branch(double dl, double dc, double dr)
+{
+    if (dl * dr <= 0.0) return ORC_MC_OFF;
+    const double c = fabs(dc), l = 2.0 * fabs(dl), r = 2.0 * fabs(dr);
+    if (c <= l && c <= r) return ORC_MC_CENTRED;
+    return l <= r ? ORC_MC_LEFT : ORC_MC_RIGHT;
+}
+
 /* Limited primitive slope of the centre cell from its two neighbours along
  * one direction (dir 0 = x, 1 = y): differences eqs. (19)-(21), projection on
  * the left eigenvectors eqs. (22)-(24), MC limiting eq. (25), projection back
- * on the right eigenvectors eq. (26). */
-void orc_limited_slope(int dir, const double wm[NV], const double w0[NV], const double wp[NV],
-                       double dwm[NV])
+ * on the right eigenvectors eq. (26).  codes (optional) receives the branch
+ * each wave's limiter takes. */
+static void limited_slope(int dir, const double wm[NV], const double w0[NV], const double wp[NV],
+                          double dwm[NV], int codes[NV])
 {
     double lam[NV], R[NV][NV], L[NV][NV];
     if (dir == 0) orc_eigen_x(w0, lam, R, L);
@@ -285,11 +297,19 @@ void orc_limited_slope(int dir, const double wm[NV], const double w0[NV], const 
     matvec(L, dC, uC);
     matvec(L, dR, uR);
     for (int k = 0; k < NV; ++k) um[k] = orc_mc(uL[k], uC[k], uR[k]);
+    if (codes)
+        for (int k = 0; k < NV; ++k) codes[k] = mc_branch(uL[k], uC[k], uR[k]);
     for (int m = 0; m < NV; ++m) {
         double s = 0.0;
         for (int k = 0; k < NV; ++k) s += um[k] * R[m][k];
         dwm[m] = s;
     }
+}
+
+void orc_limited_slope(int dir, const double wm[NV], const double w0[NV], const double wp[NV],
+                       double dwm[NV])
+{
+    limited_slope(dir, wm, w0, wp, dwm, NULL);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -307,8 +327,8 @@ void orc_limited_slope(int dir, const double wm[NV], const double w0[NV], const 
  *   eq. (31): w_hi -= k sum_{lam_a <= 0} (lam_a - lamM) (l_a . dwm) r_a  (R5)
  *   eq. (30): w_lo += k sum_{lam_a < 0} (lam0 - lam_a) (l_a . dwm) r_a
  *   eq. (32): w_lo -= k sum_{lam_a >= 0} (lam_a - lam0) (l_a . dwm) r_a  (R5) */
-void orc_trace(int dir, const double w[NV], const double dwm[NV], double k,
-               double w_lo[NV], double w_hi[NV])
+static void trace(int dir, const double w[NV], const double dwm[NV], double k,
+                  double w_lo[NV], double w_hi[NV], int codes[2])
 {
     double lam[NV], R[NV][NV], L[NV][NV];
     if (dir == 0) orc_eigen_x(w, lam, R, L);
@@ -317,6 +337,10 @@ void orc_trace(int dir, const double w[NV], const double dwm[NV], double k,
     for (int a = 1; a < NV; ++a) {
         lamM = fmax(lamM, lam[a]);
         lam0 = fmin(lam0, lam[a]);
+    }
+    if (codes) {  /* the two kinks of eqs. (27)-(28) */
+        codes[0] = lamM > 0.0;
+        codes[1] = lam0 < 0.0;
     }
 
     for (int m = 0; m < NV; ++m) {
@@ -343,9 +367,32 @@ void orc_trace(int dir, const double w[NV], const double dwm[NV], double k,
     }
 }
 
+void orc_trace(int dir, const double w[NV], const double dwm[NV], double k,
+               double w_lo[NV], double w_hi[NV])
+{
+    trace(dir, w, dwm, k, w_lo, w_hi, NULL);
+}
+
 /* ---------------------------------------------------------------------- */
 /* HLL Riemann flux (Sec. 3.3; signal speeds reading R7).                   */
 /* ---------------------------------------------------------------------- */
+
+/* Branches of the HLL flux (codes of orc_branches): which face state sets
+ * S_L (0 left, 1 right; the first on a tie), whether S_L >= 0, which sets S_R
+ * (0 left, 1 right; the first on a tie), whether S_R <= 0. */
+static void hll_branches(int dir, const double wl[NV], const double wr[NV], int codes[4])
+{
+    int iv = (dir == 0) ? IU : IV;
+    int ip = (dir == 0) ? IXX : IYY;
+    double al = sqrt(3.0 * wl[ip] / wl[IR]);
+    double ar = sqrt(3.0 * wr[ip] / wr[IR]);
+    double l0 = wl[iv] - al, l1 = wr[iv] - ar;
+    double r0 = wl[iv] + al, r1 = wr[iv] + ar;
+    codes[0] = l1 < l0;
+    codes[1] = fmin(l0, l1) >= 0.0;
+    codes[2] = r1 > r0;
+    codes[3] = fmax(r0, r1) <= 0.0;
+}
 
 void orc_hll(int dir, const double wl[NV], const double wr[NV], double flux[NV])
 {
@@ -526,6 +573,40 @@ static riemann_fn solver_fn(int solver)
     return solver == ORC_SOLVER_HLLC ? orc_hllc : orc_hll;
 }
 
+/*
+ * The four time-centred face states of one cell (1-D: the two x ones) from
+ * its primitive state w and its neighbours along x (wxm, wxp) and y (wym,
+ * wyp): limited slopes (eqs. (19)-(26)), tracing (eqs. (27)-(32)) and, in
+ * 2-D, the transverse predictor of the unsplit scheme (reading R6).  The
+ * states land at offset s of xlo, xhi, ylo, yhi.  codes (optional) receives
+ * the branches taken: per direction the six limiter codes and the two
+ * tracing kinks.
+ */
+static void cell_faces(int twod, const double *w, const double *wxm, const double *wxp, const double *wym,
+                       const double *wyp, double kx, double ky, double *xlo, double *xhi, double *ylo,
+                       double *yhi, size_t s, int codes[16])
+{
+    double dwx[NV], dwy[NV] = {0, 0, 0, 0, 0, 0};
+    limited_slope(0, wxm, w, wxp, dwx, codes);
+    trace(0, w, dwx, kx, xlo + s, xhi + s, codes ? codes + NV : NULL);
+    if (twod) {
+        limited_slope(1, wym, w, wyp, dwy, codes ? codes + 8 : NULL);
+        trace(1, w, dwy, ky, ylo + s, yhi + s, codes ? codes + 8 + NV : NULL);
+        /* transverse predictor terms (reading R6) */
+        double A[NV][NV], B[NV][NV], Adw[NV], Bdw[NV];
+        orc_jac_x(w, A);
+        orc_jac_y(w, B);
+        matvec(A, dwx, Adw);
+        matvec(B, dwy, Bdw);
+        for (int m = 0; m < NV; ++m) {
+            xlo[s + m] -= ky * Bdw[m];
+            xhi[s + m] -= ky * Bdw[m];
+            ylo[s + m] -= kx * Adw[m];
+            yhi[s + m] -= kx * Adw[m];
+        }
+    }
+}
+
 static void step_block(const orc_grid *g, double dt, int nxi, int nyi, int twod,
                        const double *Wp, const double *Uin, int gi0, int gj0,
                        double *Uout, double *Fx, double *Fy, riemann_fn riemann)
@@ -547,29 +628,9 @@ static void step_block(const orc_grid *g, double dt, int nxi, int nyi, int twod,
     #pragma omp parallel for schedule(static)
     for (int jj = 0; jj < sy; ++jj) {
         int j = twod ? jj - 1 : 0;
-        for (int i = -1; i <= nxi; ++i) {
-            const double *w = WP(i, j);
-            double dwx[NV], dwy[NV] = {0, 0, 0, 0, 0, 0};
-            orc_limited_slope(0, WP(i - 1, j), w, WP(i + 1, j), dwx);
-            size_t s = SIDX(i, j);
-            orc_trace(0, w, dwx, kx, xlo + s, xhi + s);
-            if (twod) {
-                orc_limited_slope(1, WP(i, j - 1), w, WP(i, j + 1), dwy);
-                orc_trace(1, w, dwy, ky, ylo + s, yhi + s);
-                /* transverse predictor terms (reading R6) */
-                double A[NV][NV], B[NV][NV], Adw[NV], Bdw[NV];
-                orc_jac_x(w, A);
-                orc_jac_y(w, B);
-                matvec(A, dwx, Adw);
-                matvec(B, dwy, Bdw);
-                for (int m = 0; m < NV; ++m) {
-                    xlo[s + m] -= ky * Bdw[m];
-                    xhi[s + m] -= ky * Bdw[m];
-                    ylo[s + m] -= kx * Adw[m];
-                    yhi[s + m] -= kx * Adw[m];
-                }
-            }
-        }
+        for (int i = -1; i <= nxi; ++i)
+            cell_faces(twod, WP(i, j), WP(i - 1, j), WP(i + 1, j), twod ? WP(i, j - 1) : NULL,
+                       twod ? WP(i, j + 1) : NULL, kx, ky, xlo, xhi, ylo, yhi, SIDX(i, j), NULL);
     }
 
     /* fluxes through every face of the interior */
@@ -731,6 +792,76 @@ int orc_fluxes_rs(const orc_grid *g, int solver, double dt, const double *U, dou
     return 0;
 }
 
+/*
+ * Branch pattern of one step: which side of every kink of the scheme each
+ * decision falls on (the limiter's cases, the tracing coefficients' max/min
+ * with 0, the HLL speed estimates' min/max and their clipping).  Where two
+ * states give the same pattern, the step is one smooth function on the
+ * segment between them (up to a switch and back), so a central difference
+ * across it is a derivative.  Layout, all int:
+ *   per extended cell (j = -1..ny in 2-D, 0 in 1-D; i = -1..nx; x fastest):
+ *     16 codes: x limiter codes of the six waves, x tracing kinks (lamM > 0,
+ *     lam0 < 0), then the same 8 along y (zero in 1-D);
+ *   per x face i-1/2 (j = 0..ny-1, i = 0..nx): the 4 HLL codes;
+ *   per y face j-1/2 (j = 0..ny, i = 0..nx-1), 2-D only: the 4 HLL codes.
+ */
+int64_t orc_branch_count(const orc_grid *g)
+{
+    int twod = g->ny > 1;
+    int64_t sx = g->nx + 2, sy = twod ? g->ny + 2 : 1;
+    int64_t n = 16 * sx * sy + 4 * (int64_t)(g->nx + 1) * g->ny;
+    if (twod) n += 4 * (int64_t)g->nx * (g->ny + 1);
+    return n;
+}
+
+int orc_branches(const orc_grid *g, double dt, const double *U, int *codes)
+{
+    if (!grid_ok(g)) return -1;
+    int twod = g->ny > 1;
+    int nx = g->nx, ny = g->ny;
+    const int px = nx + 4, sx = nx + 2, sy = twod ? ny + 2 : 1;
+    const double kx = dt / (2.0 * g->dx), ky = twod ? dt / (2.0 * g->dy) : 0.0;
+    double *Wp = padded_prim(g, U, 0, 0, nx, ny);
+    size_t ns = (size_t)sx * sy * NV;
+    double *xlo = malloc(ns * sizeof(double)), *xhi = malloc(ns * sizeof(double));
+    double *ylo = twod ? malloc(ns * sizeof(double)) : NULL;
+    double *yhi = twod ? malloc(ns * sizeof(double)) : NULL;
+#define WP(i, j) (Wp + ((size_t)((j) + (twod ? 2 : 0)) * px + (size_t)((i) + 2)) * NV)
+#define CELL(i, j) ((size_t)((j) + (twod ? 1 : 0)) * sx + (size_t)((i) + 1))
+    #pragma omp parallel for schedule(static)
+    for (int jj = 0; jj < sy; ++jj) {
+        int j = twod ? jj - 1 : 0;
+        for (int i = -1; i <= nx; ++i) {
+            int *c = codes + 16 * CELL(i, j);
+            for (int m = 0; m < 16; ++m) c[m] = 0;
+            cell_faces(twod, WP(i, j), WP(i - 1, j), WP(i + 1, j), twod ? WP(i, j - 1) : NULL,
+                       twod ? WP(i, j + 1) : NULL, kx, ky, xlo, xhi, ylo, yhi, CELL(i, j) * NV, c);
+        }
+    }
+    int *fxc = codes + 16 * (size_t)sx * sy;
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i <= nx; ++i)
+            hll_branches(0, xhi + CELL(i - 1, j) * NV, xlo + CELL(i, j) * NV,
+                         fxc + 4 * ((size_t)j * (nx + 1) + i));
+    if (twod) {
+        int *fyc = fxc + 4 * (size_t)(nx + 1) * ny;
+        #pragma omp parallel for schedule(static)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                hll_branches(1, yhi + CELL(i, j - 1) * NV, ylo + CELL(i, j) * NV,
+                             fyc + 4 * ((size_t)j * nx + i));
+    }
+#undef WP
+#undef CELL
+    free(Wp);
+    free(xlo);
+    free(xhi);
+    free(ylo);
+    free(yhi);
+    return 0;
+}
+
 /* Largest CFL rate of the state (reading R8): the timestep is C / s. */
 double orc_max_signal_speed(const orc_grid *g, const double *U)
 {
@@ -797,6 +928,16 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads the following parallel loops use (n >= 1); no effect without OpenMP. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 

@@ -61,10 +61,19 @@ int orc_step_cells(const orc_grid *g, double dt, const double *U, int64_t ncells
 int orc_fluxes(const orc_grid *g, double dt, const double *U, double *Fx, double *Fy);
 double orc_max_signal_speed(const orc_grid *g, const double *U);
 int orc_physical(const orc_grid *g, const double *U);
+/* Branch pattern of one step (the side of every kink each decision takes);
+ * orc_branch_count gives the number of codes.  Limiter codes: */
+#define ORC_MC_OFF 0
+#define ORC_MC_CENTRED 1
+#define ORC_MC_LEFT 2
+#define ORC_MC_RIGHT 3
+int64_t orc_branch_count(const orc_grid *g);
+int orc_branches(const orc_grid *g, double dt, const double *U, int *codes);
 /* Whole-field conversions, SoA [6][n]. */
 void orc_cons_field(int64_t n, const double *W, double *U);
 void orc_prim_field(int64_t n, const double *U, double *W);
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* Kurganov-Tadmor central scheme: numerical flux of eq. (6) and one step. */
 void orc_kt_flux(int dir, const double wl[6], const double wr[6], double flux[6]);

@@ -13,14 +13,26 @@ DEV_LIB = os.path.join(HERE, "libdevhost.so")
 DEV_SRC = os.path.join(HERE, "device_host.hip")
 
 
+# CSH_HOST_SANITIZE=1: build the harnesses' host code with AddressSanitizer
+# and UndefinedBehaviorSanitizer (a separate library; the process that loads
+# it preloads clang's ASan runtime, which carries the UBSan handlers too)
+SANITIZE = os.environ.get("CSH_HOST_SANITIZE") == "1"
+SAN_FLAGS = ["-g", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
 def _build(src: str, lib: str, headers) -> str:
+    if SANITIZE:
+        lib = lib.replace(".so", "_san.so")
     deps = [src] + [os.path.join(CSRC, f) for f in headers]
     if os.path.exists(lib) and os.path.getmtime(lib) >= max(os.path.getmtime(d) for d in deps):
         return lib
     tmp = lib + f".tmp{os.getpid()}"
     cmd = ["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
            "-ffp-contract=off", "-I", CSRC, "-I", os.path.join(ROOT, "include"),
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", src, "-o", tmp]
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *(SAN_FLAGS if SANITIZE else []),
+           src, "-o", tmp]
     subprocess.run(cmd, check=True, capture_output=True)
     os.replace(tmp, lib)
     return lib

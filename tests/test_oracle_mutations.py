@@ -91,6 +91,16 @@ MUTANTS = {
     "eigen3_shear_sign": ("R[pidx(n, ts)][cidx] = pnn;", "R[pidx(n, ts)][cidx] = -pnn;"),
     "transverse3_half": ("hi[m] -= kf[o2] * Adw[o2][m];", "hi[m] -= 0.5 * kf[o2] * Adw[o2][m];"),
     "cfl3_no_z": ("for (int k = 0; k < 3; ++k) s += (fabs(w[1 + k])", "for (int k = 0; k < 2; ++k) s += (fabs(w[1 + k])"),
+    # validity check (Sec. 2, positive-definite stress): the determinant test
+    # dropped; the finiteness test dropped (an infinite Exx leaves every sign
+    # test true)
+    "physical_no_det": ("w[IXX] > 0.0 && w[IYY] > 0.0 &&\n                   w[IXX] * w[IYY] - w[IXY] * w[IXY] > 0.0;",
+                        "w[IXX] > 0.0 && w[IYY] > 0.0;"),
+    "physical_no_isfinite": ("for (int m = 0; m < NV; ++m) good = good && isfinite(w[m]);", ""),
+    # branch pattern: the limiter's one-sided cases exchanged; the HLL S_L
+    # code on the wrong side of the tie
+    "branch_mc_sides": ("return l <= r ? ORC_MC_LEFT : ORC_MC_RIGHT;", "return l <= r ? ORC_MC_RIGHT : ORC_MC_LEFT;"),
+    "branch_hll_left": ("codes[0] = l1 < l0;", "codes[0] = l1 > l0;"),
     "fourier_mode_index": ("re[(size_t)j * mmax + m - 1] += sigma * cos(m * phi) * cell;",
                            "re[(size_t)j * mmax + m - 1] += sigma * cos((m + 1) * phi) * cell;"),
 }
@@ -114,6 +124,7 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
                    check=True, cwd=tmp_path)
     env = dict(os.environ, CSH_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_branch_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_kt_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_fourier_pins.py"),
