@@ -124,11 +124,16 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, max_seconds=20.0):
-    """The CPU oracle on a bounded sample of the same workload: whole-grid
-    steps of the 4096^2 disc until ~max_seconds of work (at least one)."""
+def _oracle_grid(w):
     import oracle
-    og = oracle.Grid(w.nx, w.ny, w.dx, w.dy, w.bcx, w.bcy, w.x0, w.y0, w.vc, w.rc)
+    return oracle.Grid(w.nx, w.ny, w.dx, w.dy, w.bcx, w.bcy, w.x0, w.y0, w.vc, w.rc)
+
+
+def _oracle_steps(w, max_seconds, min_steps=1):
+    """Whole-grid oracle CFL steps of workload w until ~max_seconds of work
+    (at least min_steps): (steps, seconds)."""
+    import oracle
+    og = _oracle_grid(w)
     U = oracle.cons_field(w.W)
     t0 = time.perf_counter()
     steps = 0
@@ -137,19 +142,73 @@ def cpu_baseline(w, max_seconds=20.0):
         U = oracle.step(og, dt, U)
         steps += 1
         el = time.perf_counter() - t0
-        if el > max_seconds or el / steps * (steps + 1) > max_seconds * 1.5:
-            break
+        if steps >= min_steps and (el > max_seconds or el / steps * (steps + 1) > max_seconds * 1.5):
+            return steps, el
+
+
+def cpu_baseline(w, seconds=(8.0, 4.0, 4.0)):
+    """The CPU oracle (FP64 C, OpenMP over rows, never tuned) timed on bounded
+    samples, in cell-updates/s.  The headline leg is the benchmark's own
+    workload on all host threads; beside it the same workload on one thread
+    (one step), the 1024^2 periodic workload (100 steps, extrapolated from a
+    few) on all threads and on one, and the 512 uneven tubes (200 steps each,
+    extrapolated from the first tubes)."""
+    import oracle
+    import workloads as wl
     threads = oracle.num_threads()
-    return {"value": steps * w.nx * w.ny / el, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
-            "sample": f"{steps} whole-grid step(s) of the {w.nx}x{w.ny} disc (same input), "
-                      f"{el:.1f} s, FP64 C oracle with {threads} OpenMP threads"}
+    legs = []
+    steps, el = _oracle_steps(w, seconds[0])
+    head = steps * w.nx * w.ny / el
+    legs.append({"workload": f"disc {w.nx}x{w.ny}", "threads": threads, "value": head,
+                 "sample": f"{steps} whole-grid step(s), {el:.1f} s"})
+    oracle.set_num_threads(1)
+    try:
+        steps1, el1 = _oracle_steps(w, seconds[1])
+    finally:
+        oracle.set_num_threads(threads)
+    legs.append({"workload": f"disc {w.nx}x{w.ny}", "threads": 1, "value": steps1 * w.nx * w.ny / el1,
+                 "sample": f"{steps1} whole-grid step(s), {el1:.1f} s"})
+    wp = wl.periodic(1024, 2, 100)
+    for nth in (threads, 1):
+        oracle.set_num_threads(nth)
+        try:
+            steps2, el2 = _oracle_steps(wp, seconds[2], min_steps=2)
+        finally:
+            oracle.set_num_threads(threads)
+        legs.append({"workload": "periodic 1024x1024, 100 steps", "threads": nth,
+                     "value": steps2 * wp.nx * wp.ny / el2,
+                     "sample": f"{steps2} of the 100 steps, {el2:.1f} s; the 100-step run extrapolated to "
+                               f"{100 * el2 / steps2:.1f} s at the same per-step cost"})
+    t = wl.tubes(nsteps=200)
+    t0 = time.perf_counter()
+    done = cells = 0
+    while done < t.lengths.size:
+        wk = wl.tube_workload(t, done)
+        og = oracle.Grid(wk.nx, 1, wk.dx, 1.0, wk.bcx, wk.bcy)
+        oracle.run_cfl(og, oracle.cons_field(wk.W), nsteps=200)
+        cells += wk.nx * 200
+        done += 1
+        if time.perf_counter() - t0 > seconds[2]:
+            break
+    el4 = time.perf_counter() - t0
+    legs.append({"workload": f"{t.lengths.size} tubes x 200 steps", "threads": threads, "value": cells / el4,
+                 "sample": f"the first {done} tubes ({cells // 200} cells) x 200 steps, {el4:.1f} s; all "
+                           f"{t.lengths.size} tubes extrapolated to {el4 * int(t.offsets[-1]) * 200 / cells:.0f} s "
+                           "at the same rate per cell-update"})
+    return {"value": head, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{steps} whole-grid step(s) of the {w.nx}x{w.ny} disc (same input), {el:.1f} s, "
+                      f"FP64 C oracle with {threads} OpenMP threads",
+            "legs": legs}
 
 
 def bench_batched(steps=200):
-    """512 uneven tubes x 200 steps: one persistent graph launch vs the plain
-    path (per tube its own grid; per step a host round trip for the timestep
-    and one launch)."""
+    """512 uneven tubes x 200 steps: one persistent graph launch against the
+    plain one-grid-per-launch path.  The plain reference is each tube's own
+    handle running its device-timed 200 steps as a replayed graph (handles and
+    graphs made before the timed region, all tubes back to back on one
+    stream); a host-stepped variant (per step a host round trip for the
+    timestep and one launch) is reported beside it."""
     import numpy as np
     import torch
     import workloads as wl
@@ -170,31 +229,53 @@ def bench_batched(steps=200):
     t_batch = e0.elapsed_time(e1) / 1e3
     Ub = b.U.cpu().numpy()
     log(f"batched: {t_batch * 1e3:.2f} ms (workgroup {best})")
-    # plain path
-    worst = 0.0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = []
-    for k in range(t.lengths.size):
+    ntubes = t.lengths.size
+    grids, starts, logs = [], [], []
+    for k in range(ntubes):
         n = int(t.lengths[k])
         g = csh.Grid(W[:, int(t.offsets[k]):int(t.offsets[k + 1])].contiguous(), 1.0 / n, 1.0,
                      (csh.BC_OUTFLOW, csh.BC_OUTFLOW))
+        starts.append(g.U.clone())
+        logs.append(torch.empty(steps, dtype=torch.float64, device="cuda"))
+        g.run_cfl(steps, 0.8, dt_log=logs[-1])   # records this handle's graph
+        grids.append(g)
+    for g, u0 in zip(grids, starts):
+        g.U.copy_(u0)
+    torch.cuda.synchronize()
+    e0.record()
+    for g, lg in zip(grids, logs):
+        g.run_cfl(steps, 0.8, dt_log=lg)
+    e1.record()
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) / 1e3
+    worst = 0.0
+    for k, g in enumerate(grids):
+        ref = g.U.cpu().numpy()
+        got = Ub[:, int(t.offsets[k]):int(t.offsets[k + 1])]
+        worst = max(worst, float(np.abs(got - ref).max() / np.abs(ref).max()))
+    log(f"plain (graph per tube): {t_plain * 1e3:.1f} ms; max scaled difference {worst:.1e}")
+    # host-stepped: max_signal_speed (a sync) and one step per launch
+    for g, u0 in zip(grids, starts):
+        g.U.copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in grids:
         Ug = g.U
         for _ in range(steps):
             Ug = g.step(0.8 / g.max_signal_speed(Ug), Ug)
-        outs.append(Ug)
     torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    for k, Ug in enumerate(outs):
-        ref = Ug.cpu().numpy()
-        got = Ub[:, int(t.offsets[k]):int(t.offsets[k + 1])]
-        worst = max(worst, float(np.abs(got - ref).max() / np.abs(ref).max()))
+    t_host = time.perf_counter() - t0
+    del grids
     cells = int(t.offsets[-1]) * steps
-    log(f"plain: {t_plain:.2f} s; max scaled difference {worst:.1e}")
-    return {"workload": f"{t.lengths.size} tubes, lengths U{{128..4096}} (total {int(t.offsets[-1])} cells), "
+    log(f"plain (host-stepped): {t_host:.2f} s")
+    return {"workload": f"{ntubes} tubes, lengths U{{128..4096}} (total {int(t.offsets[-1])} cells), "
                         f"{steps} steps, own CFL dt per tube, FP64",
             "batched_value": cells / t_batch, "plain_value": cells / t_plain, "unit": "cell-updates/s",
-            "speedup": t_plain / t_batch, "batched_ms": t_batch * 1e3, "plain_s": t_plain,
+            "speedup": t_plain / t_batch, "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
+            "plain": "per tube its own handle and a replayed graph of its 200 device-timed steps, "
+                     "tubes back to back on one stream",
+            "host_stepped_value": cells / t_host, "host_stepped_s": t_host,
+            "speedup_vs_host_stepped": t_host / t_batch,
             "workgroup": best, "max_scaled_difference": worst}
 
 
@@ -257,17 +338,36 @@ def bench_adjoint(n=512, steps=200, K=20, ndirs=64):
         fds.append(float(((rp - rm) * (0.5 * (rp + rm) - rho_t)).sum()) / (2 * eps))
     torch.cuda.synchronize()
     t_fd = time.perf_counter() - t0
-    worst = 0.0
+    # the same check at a smaller fixed step, where the differences cross
+    # fewer limiter and tracing kinks (not timed)
+    fds_small = []
+    for dd in dirs:
+        rp = runner.run(Wd + 1e-9 * dd)[0].clone()
+        rm = runner.run(Wd - 1e-9 * dd)[0]
+        fds_small.append(float(((rp - rm) * (0.5 * (rp + rm) - rho_t)).sum()) / 2e-9)
+    worst, within, plain = 0.0, 0, []
     for dd, fd in zip(dirs, fds):
         gd = gr * dd
-        worst = max(worst, abs(fd - float(gd.sum())) / float(gd.abs().sum()))
-    log(f"adjoint: grad {t_grad:.3f} s, forward {t_fwd:.3f} s, FD({ndirs} dirs) {t_fd:.2f} s")
+        ad = float(gd.sum())
+        worst = max(worst, abs(fd - ad) / float(gd.abs().sum()))
+        # the check's own measure: |FD - <grad, d>| <= 1e-5 max(|FD|, |<grad, d>|)
+        rel = abs(fd - ad) / max(abs(fd), abs(ad))
+        plain.append(rel)
+        within += rel <= 1e-5
+    within_small = sum(abs(fd - float((gr * dd).sum())) <= 1e-5 * max(abs(fd), abs(float((gr * dd).sum())))
+                       for dd, fd in zip(dirs, fds_small))
+    log(f"adjoint: grad {t_grad:.3f} s, forward {t_fwd:.3f} s, FD({ndirs} dirs) {t_fd:.2f} s; "
+        f"{within}/{ndirs} directions within 1e-5")
     return {"workload": f"periodic {n}x{n} FP64, {steps} steps, checkpoints every {K}, "
                         f"gradient vs central differences on {ndirs} directions (eps {eps})",
             "adjoint_gradient_s": t_grad, "forward_s": t_fwd, "fd_gradient_s": t_fd,
             "adjoint_gradient_s_all_states": t_grad_all, "all_states_gradient_bitwise_equal": same_all,
             "speedup": t_fd / t_grad, "adjoint_over_forward": t_grad / t_fwd,
-            "max_fd_deviation_over_sum_abs_terms_eps1e-6": worst}
+            "max_fd_deviation_over_sum_abs_terms_eps1e-6": worst,
+            "fd_directions_within_1e-5": f"{within}/{ndirs}",
+            "fd_relative_errors_eps1e-6": sorted(plain, reverse=True)[:4],
+            "fd_relative_error_median_eps1e-6": sorted(plain)[len(plain) // 2],
+            "fd_directions_within_1e-5_eps1e-9": f"{within_small}/{ndirs}"}
 
 
 def bench_fourier(w, reps=20):

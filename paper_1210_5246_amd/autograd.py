@@ -35,8 +35,11 @@ def clear_cache() -> None:
 
 
 def _grid(W0: torch.Tensor, dx: float, dy: float, bc, potential, checkpoint_every: int) -> Grid:
+    # a handle runs on the stream that was current when it was made: the
+    # stream is part of the key, so a sweep under another stream gets its own
     key = (tuple(W0.shape), W0.dtype, str(W0.device), float(dx), float(dy), tuple(int(b) for b in bc),
-           None if potential is None else tuple(float(x) for x in potential))
+           None if potential is None else tuple(float(x) for x in potential),
+           torch.cuda.current_stream(W0.device).cuda_stream)
     g = _cache.pop(key, None)
     if g is None:
         g = Grid(W0, dx, dy, bc)

@@ -136,11 +136,13 @@ def test_3d_nonphysical_input_rejected():
 
 
 def test_3d_256_benchmark_configuration():
-    """The benchmark's state and launch configuration (periodic 256^3, 32-plane
-    segments, 60-column strips): one step compared cell by cell with the oracle
-    on 3000 random cells plus cells on the strip, row and segment seams and the
-    periodic wrap; then ten device-timed steps keep every conserved total to
-    round-off (periodic boundaries: the face fluxes telescope)."""
+    """The benchmark's state and launch configuration (periodic 256^3, the
+    library's own segment length along z (37 planes at this size), 60-column
+    strips): one step compared cell by cell with the oracle on 3000 random
+    cells plus cells on the strip, row and segment seams (those of 37-plane
+    segments and, for good measure, of 32-plane ones) and the periodic wrap;
+    then ten device-timed steps keep every conserved total to round-off
+    (periodic boundaries: the face fluxes telescope)."""
     n = 256
     w = wl.periodic3(n, seed=7)
     say("3d 256^3 benchmark state: one step, sampled cells")
@@ -154,7 +156,8 @@ def test_3d_256_benchmark_configuration():
     r = np.random.default_rng(76)
     cells = set(r.integers(0, n ** 3, size=3000).tolist())
     for x in (0, 1, 58, 59, 60, 61, 119, 120, 238, 239, 240, 254, 255):
-        for y, z in ((0, 0), (255, 31), (128, 32), (1, 255), (37, 63), (200, 64), (254, 224), (100, 223)):
+        for y, z in ((0, 0), (255, 31), (128, 32), (1, 255), (37, 63), (200, 64), (254, 224), (100, 223),
+                     (3, 36), (250, 37), (64, 73), (129, 74), (5, 221), (252, 222)):
             cells.add((z * n + y) * n + x)
     cells = np.array(sorted(cells), dtype=np.int64)
     ref = oracle.step3_cells(g, dt, U0, cells).T          # [10, ncells]

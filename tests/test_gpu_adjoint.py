@@ -46,13 +46,39 @@ def gpu(W, g):
     return G
 
 
+def jac_case(kind, bc):
+    """8 cells (1-D) or 8 x 8 (2-D) cut from a smooth random field, with the
+    potential on under outflow; the cut is chosen so that no decision of the
+    step sits within a difference step of a kink (asserted by the test)."""
+    if kind == "2d":
+        w = wl.periodic(64, 61)
+        W = np.ascontiguousarray(w.W[:, 30:38, 30:38])
+        W[1:3] *= 2.0
+        g = oracle.Grid(8, 8, 1.0 / 8, 1.2 / 8, bc, bc, -0.4, -0.55, 0.8 if bc else 0.0, 0.1)
+        return W, g
+    return small_case(kind, bc, 8)
+
+
 @pytest.mark.parametrize("kind", ["1d", "2d"])
 @pytest.mark.parametrize("bc", [0, 1])
 def test_gpu_adjoint_matches_oracle_dense_jacobian(kind, bc):
-    W, g = small_case(kind, bc, 8)
+    """Rows J^T e_k of the GPU adjoint against the oracle's central-difference
+    Jacobian.  Every column's difference interval is first shown to be free of
+    kinks: the oracle's branch pattern (limiter cases, tracing and HLL
+    clipping) is the same at U - h e_b, U and U + h e_b, so the difference
+    quotient is a derivative of one smooth branch of the step."""
+    W, g = jac_case(kind, bc)
     say("adjoint vs dense Jacobian", kind, bc)
     U = oracle.cons_field(W)
     dt = 0.8 / oracle.max_signal_speed(g, U)
+    b0 = oracle.branches(g, dt, U)
+    flat = U.ravel()
+    for b in range(flat.size):
+        h = 1e-7 * max(abs(flat[b]), 1e-3)      # the step dense_jacobian takes
+        for sgn in (1.0, -1.0):
+            x = flat.copy()
+            x[b] += sgn * h
+            assert oracle.same_branches(b0, oracle.branches(g, dt, x.reshape(U.shape))), (b, sgn)
     J = oracle.dense_jacobian(g, dt, U)
     G = gpu(W, g)
     Ud = torch.from_numpy(U).to(DEV)
@@ -62,12 +88,77 @@ def test_gpu_adjoint_matches_oracle_dense_jacobian(kind, bc):
         e = torch.zeros(n, dtype=torch.float64, device=DEV)
         e[k] = 1.0
         rows[k] = G.adjoint_step(dt, Ud, e.reshape(U.shape).contiguous()).cpu().numpy().ravel()
-    # a central difference that straddles a limiter/HLL kink is not a derivative:
-    # per entry, take the closer of two difference steps (the kink is then
-    # either inside only the wider one, or far from both)
-    J2 = oracle.dense_jacobian(g, dt, U, rel=1e-8)
-    dev = np.minimum(np.abs(rows - J), np.abs(rows - J2)) / np.abs(J).max()
-    assert dev.max() < 1e-6, dev.max()
+    dev = np.abs(rows - J).max() / np.abs(J).max()
+    say("max |J^T e_k - J| / max |J|:", dev)
+    assert dev < 1e-6, dev
+
+
+def smooth_fields(r, shape, width=8.0):
+    """Six smooth zero-mean unit-std fields of the given 1-D or 2-D shape."""
+    if len(shape) == 1:
+        n = shape[0]
+        m = max(64, n)
+        return np.stack([wl.smooth_gaussian(r, (m, m), width)[0, :n] for _ in range(6)])
+    ny, nx = shape
+    m = max(64, nx, ny)
+    return np.stack([wl.smooth_gaussian(r, (m, m), width)[:ny, :nx] for _ in range(6)])
+
+
+def dot_case(shape, bc, kick, seed):
+    """A smooth random state of the given shape (cut from the periodic
+    generator, velocities doubled), optionally with the disc's potential."""
+    if len(shape) == 1:
+        n = shape[0]
+        w = wl.periodic(max(64, n + 16), seed)
+        W = np.ascontiguousarray(w.W[:, 7, 5:5 + n])
+        W[1] *= 2.0
+        g = oracle.Grid(n, 1, 1.0 / n, 1.0, bc, bc, -0.3, 0.0, 0.6 if kick else 0.0, 0.2)
+    else:
+        ny, nx = shape
+        w = wl.periodic(max(64, nx + 16, ny + 16), seed)
+        W = np.ascontiguousarray(w.W[:, 6:6 + ny, 5:5 + nx])
+        W[1:3] *= 2.0
+        g = oracle.Grid(nx, ny, 1.0 / nx, 1.3 / ny, bc, bc, -0.4, -0.55, 0.8 if kick else 0.0, 0.1)
+    return W, g
+
+
+# sizes around 60- and 62-wide wavefront strips (1-D rows and 2-D rows) and
+# tall/short grids; both boundary kinds, potential on and off
+DOT_CASES = [((58,), 0, 0), ((59,), 1, 1), ((60,), 0, 1), ((61,), 1, 0), ((121,), 0, 0), ((121,), 1, 1),
+             ((37, 121), 0, 0), ((37, 121), 1, 1), ((61, 59), 1, 0), ((70, 130), 0, 1), ((5, 61), 1, 1),
+             ((130, 7), 0, 0)]
+
+
+@pytest.mark.parametrize("shape,bc,kick", DOT_CASES)
+def test_adjoint_dot_product_against_oracle_forward(shape, bc, kick):
+    """<lam, J delta> with J delta by central differences of the ORACLE's step
+    against <J^T lam, delta> from the GPU adjoint, <= 1e-6 relative.  The
+    difference step is the largest of 1e-7, 1e-8, 1e-9 (relative to each
+    field's scale) whose interval holds no kink: the oracle's branch pattern is
+    the same at U - eps delta, U and U + eps delta."""
+    W, g = dot_case(shape, bc, kick, 65)
+    say("adjoint dot product vs oracle forward", shape, bc, kick)
+    U = oracle.cons_field(W)
+    dt = 0.8 / oracle.max_signal_speed(g, U)
+    r = np.random.default_rng(sum(shape) * 10 + bc * 2 + kick)
+    lam = r.standard_normal(U.shape)
+    scale = np.abs(U).reshape(6, -1).max(axis=1).reshape((6,) + (1,) * (U.ndim - 1))
+    delta = smooth_fields(r, U.shape[1:]) * scale
+    G = gpu(W, g)
+    got = G.adjoint_step(dt, torch.from_numpy(U).to(DEV), torch.from_numpy(lam).to(DEV)).cpu().numpy()
+    rhs = float((got * delta).sum())
+    b0 = oracle.branches(g, dt, U)
+    for eps in (1e-7, 1e-8, 1e-9):
+        if (oracle.same_branches(b0, oracle.branches(g, dt, U + eps * delta)) and
+                oracle.same_branches(b0, oracle.branches(g, dt, U - eps * delta))):
+            break
+    else:
+        pytest.fail("every difference interval crosses a kink")
+    Jd = (oracle.step(g, dt, U + eps * delta) - oracle.step(g, dt, U - eps * delta)) / (2 * eps)
+    lhs = float((lam * Jd).sum())
+    rel = abs(lhs - rhs) / abs(rhs)
+    say(f"eps {eps:g}: <lam, J d> {lhs:.12e} <J^T lam, d> {rhs:.12e} rel {rel:.1e}")
+    assert rel <= 1e-6
 
 
 # sizes around the x-part kernel's wavefronts (62 padded positions each, nx + 4
@@ -123,10 +214,24 @@ def loss_of(U, rho_target):
 def test_gradient_512_against_finite_differences():
     """512^2 periodic, 200 steps, checkpoints every 20: the gradient of
     1/2 sum (rho_200 - rho*)^2 with respect to the initial primitive fields
-    against central differences on 64 smooth directions: |fd - <grad, d>| <=
-    1e-5 sum |grad * d| for every direction and <= 1e-5 |<grad, d>| for at
-    least 60 of them; gradients with checkpoints every 20 steps, one checkpoint
-    (everything recomputed) and every state kept bitwise equal."""
+    against central differences of the GPU forward (frozen timesteps) on 64
+    smooth directions, at two fixed steps.
+
+    * eps = 1e-6: every direction within 1e-5 of sum |grad * d| (the size of
+      what the dot product sums); the count within 1e-5 relative,
+      |FD - <grad, d>| <= 1e-5 max(|FD|, |<grad, d>|), is reported.  A
+      difference over 200 x 512^2 cell updates crosses limiter and tracing
+      kinks, each an error of the order of the step, so at this step it is
+      the differences that limit the agreement (40 of 64 measured).
+    * eps = 1e-9: the kink errors have shrunk (the median error of the 64
+      falls with the step) and at least 63 of 64 directions are within 1e-5
+      relative.  The one that is not has <grad, d> = -9.4 against terms that
+      sum to 6.3e4: there the quotient's own floor (kinks at larger steps,
+      rounding of the two runs at smaller ones, ~3e-4 absolute) is 3e-5 of the
+      value.
+
+    Gradients with checkpoints every 20 steps, one checkpoint (everything
+    recomputed) and every state kept are bitwise equal."""
     w0, wt = wl.adjoint(512, 5, 6, 200, 20)
     say("target run")
     Gt = csh.Grid(torch.from_numpy(wt.W).to(DEV), wt.dx, wt.dy)
@@ -148,35 +253,30 @@ def test_gradient_512_against_finite_differences():
     (grad3,) = torch.autograd.grad(loss_of(U3, rho_t), W0c)
     assert torch.equal(dts, dts3) and torch.equal(U, U3) and torch.equal(grad, grad3)
     dirs = wl.fd_directions(512, 64)
-    worst_scaled, plain_ok = 0.0, 0
     Wd = torch.from_numpy(w0.W).to(DEV)
-    for k, d in enumerate(dirs):
-        dd = torch.from_numpy(d).to(DEV)
-        ad = float((grad * dd).sum())
-        terms = float((grad * dd).abs().sum())  # size of what the dot product sums
-        # central differences at eps = 1e-6 (the check's step) and, where that
-        # interval straddles a limiter kink somewhere in the 200 x 512^2 cell
-        # updates (an O(eps) error), at smaller steps; the closest is compared
-        devs = []
-        for eps in (1e-6, 1e-7, 1e-8, 1e-9, 1e-10):
-            rp = cag.run_frozen(Wd + eps * dd, w0.dx, w0.dy, (0, 0), dts)[0]
-            rm = cag.run_frozen(Wd - eps * dd, w0.dx, w0.dy, (0, 0), dts)[0]
+    runner = cag.FrozenRunner(Wd, w0.dx, w0.dy, (0, 0), dts)
+    stats = {}
+    for eps in (1e-6, 1e-9):
+        rel, scaled = [], []
+        for k, d in enumerate(dirs):
+            dd = torch.from_numpy(d).to(DEV)
+            ad = float((grad * dd).sum())
+            terms = float((grad * dd).abs().sum())
+            rp = runner.run(Wd + eps * dd)[0].clone()
+            rm = runner.run(Wd - eps * dd)[0]
             # L(+) - L(-) = sum (rho+ - rho-)((rho+ + rho-)/2 - rho*): the same
             # difference, formed without cancelling two sums of size ~1e4
             fd = float(((rp - rm) * (0.5 * (rp + rm) - rho_t)).sum()) / (2 * eps)
-            devs.append(abs(fd - ad))
-            if devs[-1] <= 1e-6 * abs(ad):
-                break
-        dev = min(devs)
-        plain = dev / abs(ad)
-        plain_ok += plain <= 1e-5
-        worst_scaled = max(worst_scaled, dev / terms)
-        if k % 8 == 0 or plain > 1e-5:
-            say(f"direction {k}: adjoint {ad:.6e} (terms {terms:.3e}) |fd - adjoint| {dev:.2e} "
-                f"rel {plain:.1e} rel-to-terms {dev / terms:.1e}")
-    say(f"directions within 1e-5 relative: {plain_ok}/64; worst deviation / sum|grad*d|: {worst_scaled:.2e}")
-    # The difference quotients bottom out at ~1e-4..1e-3 absolute (kinks at
-    # large eps, rounding at small eps); a direction whose derivative nearly
-    # cancels (|<grad, d>| << sum |grad * d|) cannot be resolved relatively.
-    assert worst_scaled <= 1e-5
-    assert plain_ok >= 60
+            rel.append(abs(fd - ad) / max(abs(fd), abs(ad)))
+            scaled.append(abs(fd - ad) / terms)
+            if rel[-1] > 1e-5:
+                say(f"eps {eps:g} direction {k}: adjoint {ad:.6e} (terms {terms:.3e}) fd {fd:.6e} "
+                    f"rel {rel[-1]:.1e} rel-to-terms {scaled[-1]:.1e}")
+        rel, scaled = np.array(rel), np.array(scaled)
+        stats[eps] = (int((rel <= 1e-5).sum()), float(np.median(rel)), float(scaled.max()))
+        say(f"eps {eps:g}: {stats[eps][0]}/64 within 1e-5 relative, median {stats[eps][1]:.1e}, "
+            f"worst deviation / sum|grad*d| {stats[eps][2]:.1e}")
+    assert stats[1e-6][2] <= 1e-5
+    assert stats[1e-9][2] <= 1e-6
+    assert stats[1e-9][1] < stats[1e-6][1] / 10      # the kink errors shrink with the step
+    assert stats[1e-9][0] >= 63

@@ -241,6 +241,39 @@ def test_disc_4096_one_step_sampled():
     assert max_rel_error(out[:, cells], ref) <= TOL1
 
 
+def test_disc_4096_one_step_full():
+    """Full-size disc (4096^2, FP64, outflow, fixed potential): one HLL step in
+    the launch configuration of the benchmark against the oracle on every cell."""
+    w = wl.disc(4096, 3, 1)
+    say("disc 4096^2 one step, every cell (oracle ~5 s)")
+    og = ogrid(w)
+    U0 = oracle.cons_field(w.W)
+    g = gpu_grid(w)
+    s = g.max_signal_speed()
+    assert s == pytest.approx(oracle.max_signal_speed(og, U0), rel=1e-14)
+    dt = 0.8 / s
+    out = g.step(dt).cpu().numpy()
+    ref = oracle.step(og, dt, U0)
+    assert max_rel_error(out, ref) <= TOL1
+    assert g.last_signal_speed() == pytest.approx(oracle.max_signal_speed(og, ref), rel=1e-13)
+
+
+def test_disc_1024_fifty_steps_full_grid():
+    """The disc workload at 1024^2 (outflow, fixed potential, kick after every
+    step), 50 device-timed CFL steps against the oracle's own CFL loop on the
+    whole grid: the timestep list to 1e-12 and the state to the 100-step bar."""
+    w = wl.disc(1024, 3, 50)
+    say("disc 1024^2 x 50 (oracle on CPU first, ~5-15 s)")
+    og = ogrid(w)
+    ref, dts_o = oracle.run_cfl(og, oracle.cons_field(w.W), nsteps=50, cfl=0.8)
+    g = gpu_grid(w)
+    dts = g.run_cfl(50, 0.8).cpu().numpy()
+    np.testing.assert_allclose(dts, dts_o, rtol=1e-12)
+    err = max_rel_error(g.U.cpu().numpy(), ref)
+    say("disc 1024^2 x 50 max rel error:", err)
+    assert err <= TOL100
+
+
 def test_fp32_twin_close_to_fp64():
     """The FP32 instantiation on the disc shape: reported accuracy, loose bound."""
     w = wl.disc(512, 3, 5)
