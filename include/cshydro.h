@@ -133,6 +133,27 @@ int csh_fourier_amplitudes(csh_grid *h, const void *U, double x0, double y0, dou
                            double *A);
 
 /*
+ * For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * amplitudes as csh_fourier_amplitudes, computed by the same kernels, with no
+ * allocation, no host copy and no synchronisation.
+ * The partial sums live in a statically sized device array of the library
+ * (CSH_FOURIER_MAX_M and 1024 partial rows: 1024 x 33 doubles, 264 KiB),
+ * one per GPU, held until the process ends; its address on the current device
+ * is looked up on the first call on that device (no allocation).
+ * A_dev: caller-owned DEVICE array of m_max doubles, written in stream order
+ * on the handle's stream (read it after that stream has reached this call).
+ * Arguments otherwise as csh_fourier_amplitudes; m_max > CSH_FOURIER_MAX_M is
+ * rejected (the array's limit).  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other threads)
+ * race and must be serialised by the caller.  Nothing in the array needs
+ * clearing: each call writes every partial sum it reads.
+ * Errors: CSH_ERR_ARG, CSH_ERR_HIP.
+ */
+int csh_fourier_amplitudes_noalloc(csh_grid *h, const void *U, double x0, double y0, double X, double Y,
+                                   int m_max, double *A_dev);
+
+/*
  * Fixed external potential of a flat rotation curve, Phi = vc^2/2 ln(R^2 + rc^2)
  * centred on the coordinate origin (the analytic stand-in for the halo of
  * Sec. 4.4), applied after every step as an exact operator-split kick

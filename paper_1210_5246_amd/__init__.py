@@ -60,6 +60,8 @@ _SIGNATURES = [
     ("csh_set_scheme", ctypes.c_int, [_vp, ctypes.c_int]),
     ("csh_fourier_amplitudes", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    ("csh_fourier_amplitudes_noalloc", ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_double,
+                                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, _vp]),
     ("csh_set_potential", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("csh_step", ctypes.c_int, [_vp, ctypes.c_double, _vp, _vp]),
     ("csh_max_signal_speed", ctypes.c_int, [_vp, _vp, _dp]),
@@ -175,6 +177,15 @@ class Grid:
         _check(lib().csh_fourier_amplitudes(self._h, _dev(U, self.dtype, self.n), float(x0), float(y0), float(X), float(Y),
                                             int(m_max), out))
         return list(out)
+
+    def fourier_amplitudes_noalloc(self, x0: float, y0: float, A: torch.Tensor, X: float = float("inf"),
+                                   Y: float = float("inf"), U: torch.Tensor | None = None) -> torch.Tensor:
+        """``csh_fourier_amplitudes_noalloc``: A_1..A_m (m = A.numel()) into the
+        caller's float64 GPU tensor ``A``, in stream order, with no allocation."""
+        U = self.U if U is None else U
+        _check(lib().csh_fourier_amplitudes_noalloc(self._h, _dev(U, self.dtype, self.n), float(x0), float(y0),
+                                                    float(X), float(Y), int(A.numel()), _dev(A, torch.float64)))
+        return A
 
     def set_potential(self, vc: float, rc: float, x0: float, y0: float = 0.0):
         _check(lib().csh_set_potential(self._h, vc, rc, x0, y0))

@@ -281,6 +281,28 @@ extern "C" int csh_fourier_amplitudes(csh_grid* h, const void* U, double x0, dou
     return CSH_OK;
 }
 
+extern "C" int csh_fourier_amplitudes_noalloc(csh_grid* h, const void* U, double x0, double y0, double X, double Y,
+                                              int m_max, double* A_dev)
+{
+    if (!h || !U || !A_dev) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    if (h->ny < 2) return csh_fail(CSH_ERR_ARG, "Fourier amplitudes need a 2-D grid");
+    if (m_max < 1 || m_max > CSH_FOURIER_MAX_M)
+        return csh_fail(CSH_ERR_ARG, "m_max must be in 1..CSH_FOURIER_MAX_M (the static partial sums' limit)");
+    if (!(X > 0) || !(Y > 0)) return csh_fail(CSH_ERR_ARG, "X and Y must be > 0");
+    double* partials = nullptr;
+    hipError_t e = csh::fourier_static_partials(&partials);
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("fourier (static partials): ") + hipGetErrorString(e));
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        csh::FourierArgs<T> a{static_cast<const T*>(U), h->nx, h->ny, h->dx, h->dy, x0, y0, X, Y, m_max,
+                              partials, A_dev};
+        return csh::launch_fourier<T>(a, h->stream);
+    };
+    e = h->dtype == CSH_F64 ? run(double{}) : run(float{});
+    if (e != hipSuccess) return csh_fail(CSH_ERR_HIP, std::string("fourier: ") + hipGetErrorString(e));
+    return CSH_OK;
+}
+
 extern "C" int csh_set_potential(csh_grid* h, double vc, double rc, double x0, double y0)
 {
     if (!h) return csh_fail(CSH_ERR_ARG, "h is NULL");

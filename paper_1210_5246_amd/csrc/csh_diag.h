@@ -23,4 +23,9 @@ struct FourierArgs {
 template <typename T>
 hipError_t launch_fourier(const FourierArgs<T>& a, hipStream_t s);
 
+// Partial-sum rows of the allocation-free variant: a statically sized device
+// array, kFourierBlocks x (1 + 2 kFourierMaxM) doubles per GPU.  Returns its
+// address on the current device (looked up once per device), or an error.
+hipError_t fourier_static_partials(double** ptr);
+
 }  // namespace csh

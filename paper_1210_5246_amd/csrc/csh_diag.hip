@@ -10,6 +10,8 @@
 // workgroup of one thread per partial row reduces them in a fixed order and
 // forms the amplitudes.
 // The pass reads one plane (8 B per cell in FP64) and is bound by HBM.
+#include <mutex>
+
 #include "csh_device.h"
 #include "csh_diag.h"
 
@@ -153,5 +155,36 @@ hipError_t launch_fourier(const FourierArgs<T>& a, hipStream_t s)
 
 template hipError_t launch_fourier<double>(const FourierArgs<double>&, hipStream_t);
 template hipError_t launch_fourier<float>(const FourierArgs<float>&, hipStream_t);
+
+// ---- statically sized partial sums (the allocation-free entry point) ----------------------------
+
+// In host code `scratch` names a host-side stand-in, not device memory: only
+// the address hipGetSymbolAddress returns for the current device may be handed
+// to a kernel or a copy.
+namespace {
+constexpr size_t kStaticPartials = (size_t)kFourierBlocks * (1 + 2 * kFourierMaxM);
+static __device__ __align__(256) double scratch[kStaticPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t fourier_static_partials(double** ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 }  // namespace csh
