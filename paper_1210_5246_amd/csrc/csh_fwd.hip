@@ -99,15 +99,19 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(StepArgs<T> p)
         Prim<T> Wa = to_prim(Ua, ia), Wb = to_prim(Ub, ib), Wc = to_prim(Uc, ic);
         Prim<T> yhi_prev{};  // high y-face state of the cell below (primitive, axes not exchanged)
         Cons<T> acc{};       // update of the cell below, all but its high y-face flux
+        Prim<T> dly = sub(Wb, Wa);  // y difference below the row: the previous row's upper one
 
         // one row: (Um, Wm) row r-1 (refilled with row r+2), (U0, W0, ir0) row r, Wp row r+1
         auto row = [&](int r, Cons<T>& Um, Prim<T>& Wm, T& irm, const Cons<T>& U0, const Prim<T>& W0, T ir0,
                        const Prim<T>& Wp) {
             const Cons<T> Unext = load_row(min(r + 2, y1 + 1));  // past the window's end: a row already read
 
-            // face states of (c, r): x neighbours from the adjacent lanes, y from the row window
-            const Faces<T> fs =
-                face_states<T, true>(W0, ir0, lane_shift<-1>(W0), lane_shift<+1>(W0), Wm, Wp, kx, ky);
+            // face states of (c, r): the x differences from the right neighbour (a lane
+            // shift), the left one that of the lane to the left; the y difference below
+            // the row carried from the row before
+            const Prim<T> drx = sub(lane_shift<+1>(W0), W0), dry = sub(Wp, W0);
+            const Faces<T> fs = face_states_d<T, true>(W0, ir0, lane_shift<-1>(drx), drx, dly, dry, kx, ky);
+            dly = dry;
 
             if (r >= y0) {
                 // y face r - 1/2 between the cell below (its high state) and this cell (low state)
