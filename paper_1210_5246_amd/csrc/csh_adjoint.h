@@ -43,12 +43,13 @@ CSH_HD void eig_vjp(const P& w, double ir, const E& e, const E& eb, P& wb, doubl
     ipb += w.pxy * eb.q;
     // ip = 1 / pxx
     wb.pxx += -e.ip * e.ip * ipb;
-    // h2a = k / c ; h2c = 0.5 / c ; a = sqrt3 c
-    cb += -e.h2a / e.c * eb.h2a;
-    cb += -e.h2c / e.c * eb.h2c;
+    // h2a = k / c ; h2c = 0.5 / c ; a = sqrt3 c  (1 / c = 2 h2c)
+    const double ic = 2.0 * e.h2c;
+    cb += -e.h2a * ic * eb.h2a;
+    cb += -e.h2c * ic * eb.h2c;
     cb += 1.7320508075688772935 * eb.a;
     // c = sqrt(pxx ir)
-    const double tb = cb / (2.0 * e.c);
+    const double tb = cb * e.h2c;
     wb.pxx += ir * tb;
     irb += w.pxx * tb;
 }
@@ -60,16 +61,17 @@ CSH_HD void project_vjp(const P& w, const E& e, const P& d, const A6& ab, P& wb,
     const double hb = ab.a2 - ab.a5, sb = ab.a2 + ab.a5;
     // a3 = d.r - w.r d.pxx ip / 3
     db.r += ab.a3;
-    wb.r += -d.pxx * e.ip / 3.0 * ab.a3;
-    db.pxx += -w.r * e.ip / 3.0 * ab.a3;
-    eb.ip += -w.r * d.pxx / 3.0 * ab.a3;
+    constexpr double third = 1.0 / 3.0, sixth = 1.0 / 6.0;
+    wb.r += -d.pxx * e.ip * third * ab.a3;
+    db.pxx += -w.r * e.ip * third * ab.a3;
+    eb.ip += -w.r * d.pxx * third * ab.a3;
     // a4 = d.pyy - 2 q d.pxy + (4 q^2 - pyy ip) d.pxx / 3
     db.pyy += ab.a4;
-    eb.q += (-2.0 * d.pxy + 8.0 * e.q * d.pxx / 3.0) * ab.a4;
+    eb.q += (-2.0 * d.pxy + 8.0 * e.q * d.pxx * third) * ab.a4;
     db.pxy += -2.0 * e.q * ab.a4;
-    wb.pyy += -e.ip * d.pxx / 3.0 * ab.a4;
-    eb.ip += -w.pyy * d.pxx / 3.0 * ab.a4;
-    db.pxx += (4.0 * e.q * e.q - w.pyy * e.ip) / 3.0 * ab.a4;
+    wb.pyy += -e.ip * d.pxx * third * ab.a4;
+    eb.ip += -w.pyy * d.pxx * third * ab.a4;
+    db.pxx += (4.0 * e.q * e.q - w.pyy * e.ip) * third * ab.a4;
     // h = (q d.u - d.v) h2c
     const double X = e.q * d.u - d.v;
     const double Xb = e.h2c * hb;
@@ -88,8 +90,8 @@ CSH_HD void project_vjp(const P& w, const E& e, const P& d, const A6& ab, P& wb,
     db.u += e.h2a * t2b;
     eb.h2a += d.u * t2b;
     // t1 = d.pxx ip / 6
-    db.pxx += e.ip / 6.0 * t1b;
-    eb.ip += d.pxx / 6.0 * t1b;
+    db.pxx += e.ip * sixth * t1b;
+    eb.ip += d.pxx * sixth * t1b;
 }
 
 // backproject(w, e, alpha) -> d
@@ -313,7 +315,7 @@ CSH_HD void to_cons_vjp(const P& w, const C& Ub, P& wb)
 // to_prim(U): u = mx ir, v = my ir, pxx = exx - mx u, pxy = exy - mx v, pyy = eyy - my v
 CSH_HD void to_prim_vjp(const C& U, const P& wb, C& Ub)
 {
-    const double ir = 1.0 / U.r;
+    const double ir = rcp(U.r);
     const double u = U.mx * ir, v = U.my * ir;
     Ub.exx += wb.pxx;
     Ub.exy += wb.pxy;
@@ -348,7 +350,7 @@ CSH_HD void hll_vjp(const P& wl, const P& wr, const C& Fb, P& wlb, P& wrb)
     const double C1 = L.w.u + L.a, D1 = R.w.u + R.a;
     const double sl = fmin(fmin(A1, B1), 0.0);
     const double sr = fmax(fmax(C1, D1), 0.0);
-    const double inv = 1.0 / (sr - sl);
+    const double inv = rcp(sr - sl);
     const double slr = sl * sr;
     const C FL = flux_x(L.w, L.U), FR = flux_x(R.w, R.U);
     const double fl[6] = {FL.r, FL.mx, FL.my, FL.exx, FL.exy, FL.eyy};
@@ -393,11 +395,12 @@ CSH_HD void hll_vjp(const P& wl, const P& wr, const C& Fb, P& wlb, P& wrb)
     to_cons_vjp(R.w, URb, wrb);
     wlb.u += ulwb;
     wrb.u += urwb;
-    // a = sqrt(3 pxx / r)
-    wlb.pxx += L.a / (2.0 * L.w.pxx) * alb;
-    wlb.r += -L.a / (2.0 * L.w.r) * alb;
-    wrb.pxx += R.a / (2.0 * R.w.pxx) * arb;
-    wrb.r += -R.a / (2.0 * R.w.r) * arb;
+    // a = sqrt(3 pxx / r): da/dpxx = a / (2 pxx), da/dr = -a / (2 r)
+    const double hl = 0.5 * L.a * alb, hr = 0.5 * R.a * arb;
+    wlb.pxx += hl * rcp(L.w.pxx);
+    wlb.r -= hl * rcp(L.w.r);
+    wrb.pxx += hr * rcp(R.w.pxx);
+    wrb.r -= hr * rcp(R.w.r);
 }
 
 // the fixed-field kick is affine in U with a constant Jacobian K; lam' = K^T lam
@@ -430,6 +433,8 @@ struct AdjArgs {
     int nx, ny, bcx, bcy;
     int ex, ey;          // extended grid: ex = nx + 2, ey = ny + 2 (1-D: 1)
     double dx, dy, dt;
+    double kx, ky;       // dt / (2 dx), dt / (2 dy) (1-D: ky = 0)
+    double cx, cy;       // dt / dx, dt / dy
     double vc2, rc2, x0, y0;
     const double* U;     // [6][ny][nx]
     const double* lam1;  // lam^{n+1}
@@ -440,6 +445,15 @@ struct AdjArgs {
     double* XS;          // [6][ey][nx + 4]: per padded position (column -2 .. nx + 1 of an extended
                          // row), SELF and the x part's shares summed
 };
+
+// the step factors of AdjArgs from dt, dx, dy (IEEE divisions, once per call)
+CSH_HD void set_step_factors(AdjArgs& a)
+{
+    a.kx = a.dt / (2.0 * a.dx);
+    a.ky = a.ey > 1 ? a.dt / (2.0 * a.dy) : 0.0;
+    a.cx = a.dt / a.dx;
+    a.cy = a.ey > 1 ? a.dt / a.dy : 0.0;
+}
 
 enum { XHI = 0, XLO = 1, YHI = 2, YLO = 3 };
 enum { SELF = 0, DOWN = 1, UP = 2 };
@@ -460,11 +474,25 @@ CSH_HD void store_p(double* B, size_t plane, size_t slot, size_t idx, const P& v
     b[5 * plane + idx] = v.pyy;
 }
 
+// map_index for -2n <= i < 3n (the reverse pass reads at most two cells past
+// the extended ring, so any n >= 1 is covered): no division
+CSH_HD int map_wide(int i, int n, int bc)
+{
+    if (bc == 0) {
+        if (i < 0) i += n;
+        if (i < 0) i += n;
+        if (i >= n) i -= n;
+        if (i >= n) i -= n;
+        return i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
 // primitive state of the (possibly ghost) cell (i, j)
 CSH_HD P prim_at(const AdjArgs& a, int i, int j, bool twod)
 {
-    const int gi = map_index(i, a.nx, a.bcx);
-    const int gj = twod ? map_index(j, a.ny, a.bcy) : 0;
+    const int gi = map_wide(i, a.nx, a.bcx);
+    const int gj = twod ? map_wide(j, a.ny, a.bcy) : 0;
     return to_prim(load_cons<double>(a.U, (size_t)a.nx * a.ny, (size_t)gj * a.nx + gi));
 }
 
@@ -477,14 +505,14 @@ CSH_HD C lam_prime(const AdjArgs& a, int i, int j, bool twod)
     if (a.vc2 == 0.0) return l;
     const double x = a.x0 + (i + 0.5) * a.dx;
     const double y = twod ? a.y0 + (j + 0.5) * a.dy : 0.0;
-    const double f = -a.vc2 / (x * x + y * y + a.rc2);
+    const double f = -a.vc2 * rcp(x * x + y * y + a.rc2);
     return kick_vjp(l, a.dt, f * x, f * y);
 }
 
 template <bool TWOD>
 CSH_HD void faces_cell(const AdjArgs& a, int i, int j)
 {
-    const double kx = a.dt / (2.0 * a.dx), ky = TWOD ? a.dt / (2.0 * a.dy) : 0.0;
+    const double kx = a.kx, ky = TWOD ? a.ky : 0.0;
     const P W0 = prim_at(a, i, j, TWOD);
     const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
     const P Wm = TWOD ? prim_at(a, i, j - 1, TWOD) : W0, Wp = TWOD ? prim_at(a, i, j + 1, TWOD) : W0;
@@ -525,7 +553,7 @@ CSH_HD void hll_cell(const AdjArgs& a, int i, int j)
         const int jj = TWOD ? j : 0;
         const C lp = (i + 1 <= a.nx - 1) ? lam_prime(a, i + 1, jj, TWOD) : z;
         const C lm = (i >= 0) ? lam_prime(a, i, jj, TWOD) : z;
-        const C Fb = csub(lp, lm, a.dt / a.dx);
+        const C Fb = csub(lp, lm, a.cx);
         P wlb = zero_p(), wrb = zero_p();
         hll_vjp(load_p(a.FS, ne, XHI, e), load_p(a.FS, ne, XLO, e + 1), Fb, wlb, wrb);
         store_p(a.FSb, ne, XHI, e, wlb);
@@ -534,7 +562,7 @@ CSH_HD void hll_cell(const AdjArgs& a, int i, int j)
     if (TWOD && j <= a.ny - 1 && i >= 0 && i < a.nx) {
         const C lp = (j + 1 <= a.ny - 1) ? lam_prime(a, i, j + 1, true) : z;
         const C lm = (j >= 0) ? lam_prime(a, i, j, true) : z;
-        const C Gb = csub(lp, lm, a.dt / a.dy);
+        const C Gb = csub(lp, lm, a.cy);
         P wlb = zero_p(), wrb = zero_p();
         hll_vjp(swap(load_p(a.FS, ne, YHI, e)), swap(load_p(a.FS, ne, YLO, e + a.ex)), swap(Gb), wlb, wrb);
         store_p(a.FSb, ne, YHI, e, swapb(wlb));
@@ -560,7 +588,7 @@ CSH_HD Faces<double> load_face_adjoints(const AdjArgs& a, size_t ne, size_t e, b
 // (its share), DOWN, UP
 CSH_HD void cells_cell_y(const AdjArgs& a, int i, int j)
 {
-    const double ky = a.dt / (2.0 * a.dy);
+    const double ky = a.ky;
     const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
     const P W0 = prim_at(a, i, j, true);
     const P Wm = prim_at(a, i, j - 1, true), Wp = prim_at(a, i, j + 1, true);
@@ -577,7 +605,7 @@ CSH_HD void cells_cell_y(const AdjArgs& a, int i, int j)
 template <bool TWOD>
 CSH_HD void cells_x_vjp(const AdjArgs& a, int i, int j, P& b0, P& bl, P& br)
 {
-    const double kx = a.dt / (2.0 * a.dx);
+    const double kx = a.kx;
     const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
     const P W0 = prim_at(a, i, j, TWOD);
     const P Wl = prim_at(a, i - 1, j, TWOD), Wr = prim_at(a, i + 1, j, TWOD);
@@ -637,6 +665,250 @@ CSH_HD void gather_cell(const AdjArgs& a, int i, int j)
         for (int v = 0; v < ny_; ++v) acc(wb, pad_sum<TWOD>(a, px[u], py[v]));
     const size_t plane = (size_t)a.nx * a.ny, c = (size_t)j * a.nx + i;
     C out = lam_prime(a, i, j, TWOD);
+    to_prim_vjp(load_cons<double>(a.U, plane, c), wb, out);
+    store_cons(a.lam0, plane, c, out);
+}
+
+// ---- the tiled two-kernel reverse pass (2-D) ----------------------------------------------
+//
+// Kernel A (faces and fluxes) and kernel B (face states and gather) replace the
+// five one-thread-per-cell stages on 2-D grids.  Each works on a tile held in
+// LDS, so the face states, the shares of the face-state reverse pass and
+// their sums never travel through device memory; only the face-state
+// adjoints (FSb) pass from A to B.
+//
+// Periodic axes are treated as a pure wrap: a virtual cell outside [0, n) is
+// the wrapped cell (its state, its lam' and its face-state adjoints), every
+// face is a real face, and an output cell gathers only the shares that land on
+// itself.  Outflow axes keep the extended ring (cells -1 and n, lam' = 0
+// outside [0, n)), and the shares landing on ghost positions (-2, -1, n,
+// n + 1) are folded into the boundary cell.  Both are the transpose of the
+// same forward step; they differ from the five-stage pass only in the order
+// of the sums.
+//
+// The bodies below are the per-thread work of each phase between the
+// workgroup barriers, written so a CPU loop over tiles, phases and threads
+// runs them unchanged (tests/host).
+
+// kernel A: a tile of kA_TX x kA_TY extended cells, one thread per cell
+constexpr int kA_TX = 32, kA_TY = 8, kA_THREADS = kA_TX * kA_TY;
+constexpr int kA_WX = kA_TX + 3, kA_WY = kA_TY + 3;  // states: cells [X0 - 1, X0 + TX + 2)
+constexpr int kA_FX = kA_TX + 1, kA_FY = kA_TY + 1;  // face states: cells [X0, X0 + TX + 1)
+constexpr int kA_NW = kA_WX * kA_WY, kA_NF = kA_FX * kA_FY;
+constexpr int kA_LDS = 6 * kA_NW + 24 * kA_NF;       // doubles of LDS
+
+// kernel B: a tile of kB_W x kB_H virtual cells (one wavefront per row), the
+// outputs its inner (kB_W - 2) x (kB_H - 2) cells
+constexpr int kB_W = 64, kB_H = 8, kB_THREADS = kB_W * kB_H;
+constexpr int kB_OX = kB_W - 2, kB_OY = kB_H - 2;
+enum { SH_LEFT = 0, SH_RIGHT = 1, SH_DOWN = 2, SH_UP = 3, SH_TOT = 4 };
+constexpr int kB_SX = kB_W + 2, kB_SY = kB_H + 2, kB_NS = kB_SX * kB_SY;  // states: the tile and a ring
+constexpr int kB_LDS = 5 * 6 * kB_THREADS + 6 * kB_NS;  // doubles of LDS (the states after the shares)
+
+CSH_HD void lds_put(double* L, int stride, int base, int k, const P& v)
+{
+    L[base + 0 * stride + k] = v.r;
+    L[base + 1 * stride + k] = v.u;
+    L[base + 2 * stride + k] = v.v;
+    L[base + 3 * stride + k] = v.pxx;
+    L[base + 4 * stride + k] = v.pxy;
+    L[base + 5 * stride + k] = v.pyy;
+}
+CSH_HD P lds_get(const double* L, int stride, int base, int k)
+{
+    return {L[base + k], L[base + stride + k], L[base + 2 * stride + k], L[base + 3 * stride + k],
+            L[base + 4 * stride + k], L[base + 5 * stride + k]};
+}
+
+// lam' of a virtual cell: wrapped on periodic axes; zero outside the grid on outflow ones
+CSH_HD C lam_prime_virtual(const AdjArgs& a, int i, int j)
+{
+    if (a.bcx != 0 && (i < 0 || i >= a.nx)) return zero_c();
+    if (a.bcy != 0 && (j < 0 || j >= a.ny)) return zero_c();
+    return lam_prime(a, map_wide(i, a.nx, a.bcx), map_wide(j, a.ny, a.bcy), true);
+}
+
+// A1: primitive states of the cells [X0 - 1, X0 + TX + 2) x [Y0 - 1, Y0 + TY + 2)
+// (coordinates past [-2, n + 1] are clamped into it: those cells only feed
+// face states of cells beyond the extended ring, which no face uses)
+CSH_HD void tileA_states(const AdjArgs& a, int X0, int Y0, int t, double* L)
+{
+    for (int k = t; k < kA_NW; k += kA_THREADS) {
+        const int i0 = X0 - 1 + k % kA_WX, j0 = Y0 - 1 + k / kA_WX;
+        const int i = i0 < -2 ? -2 : (i0 > a.nx + 1 ? a.nx + 1 : i0);
+        const int j = j0 < -2 ? -2 : (j0 > a.ny + 1 ? a.ny + 1 : j0);
+        lds_put(L, kA_NW, 0, k, prim_at(a, i, j, true));
+    }
+}
+
+// A2: face states of the cells [X0, X0 + TX + 1) x [Y0, Y0 + TY + 1)
+CSH_HD void tileA_faces(const AdjArgs& a, int t, double* L)
+{
+    double* F = L + 6 * kA_NW;
+    for (int k = t; k < kA_NF; k += kA_THREADS) {
+        const int lx = k % kA_FX + 1, ly = k / kA_FX + 1;  // position in the state block
+        const int c = ly * kA_WX + lx;
+        const P W0 = lds_get(L, kA_NW, 0, c);
+        const Faces<double> f = face_states<double, true>(W0, rcp(W0.r), lds_get(L, kA_NW, 0, c - 1),
+                                                          lds_get(L, kA_NW, 0, c + 1), lds_get(L, kA_NW, 0, c - kA_WX),
+                                                          lds_get(L, kA_NW, 0, c + kA_WX), a.kx, a.ky);
+        lds_put(F, kA_NF, XHI * 6 * kA_NF, k, f.xhi);
+        lds_put(F, kA_NF, XLO * 6 * kA_NF, k, f.xlo);
+        lds_put(F, kA_NF, YHI * 6 * kA_NF, k, f.yhi);
+        lds_put(F, kA_NF, YLO * 6 * kA_NF, k, f.ylo);
+    }
+}
+
+// A3: the extended cell e = (X0 + t % TX, Y0 + t / TX): the flux adjoints of its
+// high x and y faces, through HLL into the adjoints of the two face states of
+// each (written to FSb); the slots of the ring that no face writes are cleared
+CSH_HD void tileA_fluxes(const AdjArgs& a, int X0, int Y0, int t, const double* L)
+{
+    const double* F = L + 6 * kA_NW;
+    const int i = X0 + t % kA_TX, j = Y0 + t / kA_TX;
+    if (i > a.nx || j > a.ny) return;  // outside the extended grid
+    const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
+    const int k = (t / kA_TX) * kA_FX + t % kA_TX;  // e in the face-state block
+    if (i == a.nx) store_p(a.FSb, ne, XHI, e, zero_p());
+    if (i == -1) store_p(a.FSb, ne, XLO, e, zero_p());
+    if (j == a.ny) store_p(a.FSb, ne, YHI, e, zero_p());
+    if (j == -1) store_p(a.FSb, ne, YLO, e, zero_p());
+    if (i == a.nx && j == a.ny) return;
+    const C l0 = lam_prime_virtual(a, i, j);
+    if (i <= a.nx - 1) {  // x face i + 1/2
+        const C Fb = csub(lam_prime_virtual(a, i + 1, j), l0, a.cx);
+        P wlb = zero_p(), wrb = zero_p();
+        hll_vjp(lds_get(F, kA_NF, XHI * 6 * kA_NF, k), lds_get(F, kA_NF, XLO * 6 * kA_NF, k + 1), Fb, wlb, wrb);
+        store_p(a.FSb, ne, XHI, e, wlb);
+        store_p(a.FSb, ne, XLO, e + 1, wrb);
+    }
+    if (j <= a.ny - 1) {  // y face j + 1/2
+        const C Gb = csub(lam_prime_virtual(a, i, j + 1), l0, a.cy);
+        P wlb = zero_p(), wrb = zero_p();
+        hll_vjp(swap(lds_get(F, kA_NF, YHI * 6 * kA_NF, k)), swap(lds_get(F, kA_NF, YLO * 6 * kA_NF, k + kA_FX)),
+                swap(Gb), wlb, wrb);
+        store_p(a.FSb, ne, YHI, e, swapb(wlb));
+        store_p(a.FSb, ne, YLO, e + a.ex, swapb(wrb));
+    }
+}
+
+// index of a virtual cell in the extended face-state arrays, -1 for a cell
+// beyond the ring [-1, n] (its shares reach no output: on an outflow axis its
+// face states feed no face, on a periodic one it is not next to an output);
+// a ring cell of a periodic axis is the wrapped cell
+CSH_HD long ext_of_virtual(const AdjArgs& a, int i, int j)
+{
+    if (i < -1 || i > a.nx || j < -1 || j > a.ny) return -1;
+    if (a.bcx == 0) i = map_wide(i, a.nx, 0);
+    if (a.bcy == 0) j = map_wide(j, a.ny, 0);
+    return (long)ext_index(a, i, j);
+}
+
+// B0: primitive states of the tile and its ring, cells [X0 - 2, X0 + 64) x
+// [Y0 - 2, Y0 + 8) (coordinates clamped into [-2, n + 1], as in A1)
+CSH_HD void tileB_states(const AdjArgs& a, int X0, int Y0, int t, double* L)
+{
+    double* S = L + 5 * 6 * kB_THREADS;
+    for (int k = t; k < kB_NS; k += kB_THREADS) {
+        const int i0 = X0 - 2 + k % kB_SX, j0 = Y0 - 2 + k / kB_SX;
+        const int i = i0 < -2 ? -2 : (i0 > a.nx + 1 ? a.nx + 1 : i0);
+        const int j = j0 < -2 ? -2 : (j0 > a.ny + 1 ? a.ny + 1 : j0);
+        lds_put(S, kB_NS, 0, k, prim_at(a, i, j, true));
+    }
+}
+
+// B1: the face-state reverse pass of the virtual cell at lane l, row w of the
+// tile (X0 - 1 + l, Y0 - 1 + w): its own share returned, the four it gives its
+// neighbours written to LDS
+CSH_HD P tileB_shares(const AdjArgs& a, int X0, int Y0, int t, double* L)
+{
+    const double* S = L + 5 * 6 * kB_THREADS;
+    const int l = t % kB_W, w = t / kB_W;
+    const int i = X0 - 1 + l, j = Y0 - 1 + w;
+    const int c = (w + 1) * kB_SX + (l + 1);  // the cell in the state block
+    P b0 = zero_p();
+    const long e = ext_of_virtual(a, i, j);
+    // the y part first, its two neighbour shares stored before the x part
+    // starts (fewer values live at once)
+    Faces<double> fb{zero_p(), zero_p(), zero_p(), zero_p()};
+    P W0 = zero_p();
+    if (e >= 0) {
+        fb = load_face_adjoints(a, (size_t)a.ex * a.ey, (size_t)e, true);
+        W0 = lds_get(S, kB_NS, 0, c);
+    }
+    {
+        P bm = zero_p(), bp = zero_p();
+        if (e >= 0)
+            face_states_vjp_y(W0, lds_get(S, kB_NS, 0, c - kB_SX), lds_get(S, kB_NS, 0, c + kB_SX), a.ky, fb, b0, bm,
+                              bp);
+        lds_put(L, kB_THREADS, SH_DOWN * 6 * kB_THREADS, t, bm);
+        lds_put(L, kB_THREADS, SH_UP * 6 * kB_THREADS, t, bp);
+    }
+    P bl = zero_p(), br = zero_p();
+    if (e >= 0)
+        face_states_vjp_x<true>(W0, lds_get(S, kB_NS, 0, c - 1), lds_get(S, kB_NS, 0, c + 1), a.kx, fb, b0, bl, br);
+    lds_put(L, kB_THREADS, SH_LEFT * 6 * kB_THREADS, t, bl);
+    lds_put(L, kB_THREADS, SH_RIGHT * 6 * kB_THREADS, t, br);
+    return b0;
+}
+
+// B2: everything that lands on the position of lane l, row w from inside the tile
+CSH_HD P tileB_total(int t, const P& self, const double* L)
+{
+    const int l = t % kB_W, w = t / kB_W;
+    P s = self;
+    if (l + 1 < kB_W) acc(s, lds_get(L, kB_THREADS, SH_LEFT * 6 * kB_THREADS, t + 1));
+    if (l >= 1) acc(s, lds_get(L, kB_THREADS, SH_RIGHT * 6 * kB_THREADS, t - 1));
+    if (w >= 1) acc(s, lds_get(L, kB_THREADS, SH_UP * 6 * kB_THREADS, t - kB_W));
+    if (w + 1 < kB_H) acc(s, lds_get(L, kB_THREADS, SH_DOWN * 6 * kB_THREADS, t + kB_W));
+    return s;
+}
+
+CSH_HD void tileB_put_total(int t, const P& s, double* L) { lds_put(L, kB_THREADS, SH_TOT * 6 * kB_THREADS, t, s); }
+
+// what lands on tile position (lp, wp), lp in [-1, kB_W], wp in [-1, kB_H]:
+// the total inside the tile, or the one share a tile cell gives a position just
+// outside it (the cells beyond it feed only ghost positions of outflow axes
+// through shares that are zero: they lie past the extended ring)
+CSH_HD P tileB_landing(int lp, int wp, const double* L)
+{
+    const bool xin = lp >= 0 && lp < kB_W, yin = wp >= 0 && wp < kB_H;
+    if (xin && yin) return lds_get(L, kB_THREADS, SH_TOT * 6 * kB_THREADS, wp * kB_W + lp);
+    if (yin && lp == -1) return lds_get(L, kB_THREADS, SH_LEFT * 6 * kB_THREADS, wp * kB_W);
+    if (yin && lp == kB_W) return lds_get(L, kB_THREADS, SH_RIGHT * 6 * kB_THREADS, wp * kB_W + kB_W - 1);
+    if (xin && wp == -1) return lds_get(L, kB_THREADS, SH_DOWN * 6 * kB_THREADS, lp);
+    if (xin && wp == kB_H) return lds_get(L, kB_THREADS, SH_UP * 6 * kB_THREADS, (kB_H - 1) * kB_W + lp);
+    return zero_p();
+}
+
+// positions whose shares belong to output coordinate i on one axis: itself, and
+// on an outflow axis the ghost positions the boundary cell stands for
+CSH_HD int fold_positions(int i, int n, int bc, int* p)
+{
+    int k = 0;
+    p[k++] = i;
+    if (bc != 0) {
+        if (i == 0) { p[k++] = -1; p[k++] = -2; }
+        if (i == n - 1) { p[k++] = n; p[k++] = n + 1; }
+    }
+    return k;
+}
+
+// B3: the output cell at lane l, row w (inner cells only): the folded total of
+// the shares on its positions, through W(U), plus lam' itself
+CSH_HD void tileB_gather(const AdjArgs& a, int X0, int Y0, int t, const double* L)
+{
+    const int l = t % kB_W, w = t / kB_W;
+    if (l < 1 || l > kB_OX || w < 1 || w > kB_OY) return;
+    const int i = X0 - 1 + l, j = Y0 - 1 + w;
+    if (i >= a.nx || j >= a.ny) return;
+    int px[5], py[5];
+    const int nx_ = fold_positions(i, a.nx, a.bcx, px), ny_ = fold_positions(j, a.ny, a.bcy, py);
+    P wb = zero_p();
+    for (int u = 0; u < nx_; ++u)
+        for (int v = 0; v < ny_; ++v) acc(wb, tileB_landing(px[u] - (X0 - 1), py[v] - (Y0 - 1), L));
+    const size_t plane = (size_t)a.nx * a.ny, c = (size_t)j * a.nx + i;
+    C out = lam_prime(a, i, j, true);
     to_prim_vjp(load_cons<double>(a.U, plane, c), wb, out);
     store_cons(a.lam0, plane, c, out);
 }

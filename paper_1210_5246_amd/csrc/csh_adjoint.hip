@@ -39,15 +39,16 @@ namespace csh {
 template <bool TWOD, int STAGE>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a)
 {
-    const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    // cell counts stay below 2^31 (a plane is smaller than 4 GiB): 32-bit index arithmetic
+    const unsigned t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (STAGE == 4) {  // interior cells
-        if (t >= (int64_t)a.nx * a.ny) return;
-        gather_cell<TWOD>(a, (int)(t % a.nx), (int)(t / a.nx));
+        if (t >= (unsigned)a.nx * (unsigned)a.ny) return;
+        gather_cell<TWOD>(a, (int)(t % (unsigned)a.nx), (int)(t / (unsigned)a.nx));
         return;
     }
-    if (t >= (int64_t)a.ex * a.ey) return;  // extended cells
-    const int i = (int)(t % a.ex) - 1;
-    const int j = TWOD ? (int)(t / a.ex) - 1 : 0;
+    if (t >= (unsigned)a.ex * (unsigned)a.ey) return;  // extended cells
+    const int i = (int)(t % (unsigned)a.ex) - 1;
+    const int j = TWOD ? (int)(t / (unsigned)a.ex) - 1 : 0;
     if (STAGE == 1) faces_cell<TWOD>(a, i, j);
     if (STAGE == 2) hll_cell<TWOD>(a, i, j);
     if constexpr (STAGE == 3 && TWOD) cells_cell_y(a, i, j);
@@ -79,6 +80,45 @@ __global__ __launch_bounds__(256) void adjoint_xsum_kernel(AdjArgs a)
         store_p(a.XS, (size_t)(a.nx + 4) * a.ey, 0, xs_index(a, i, j), sum);
 }
 
+// The tiled reverse pass of 2-D grids.  Kernel A: a workgroup per tile of
+// 32 x 8 extended cells (one thread each): the states of the tile and a
+// ring into LDS, the face states of the tile plus one column and one row,
+// then per cell the flux adjoints of its high x and y faces through HLL into
+// the face-state adjoints (FSb, device memory).  75.5 KB of LDS.
+__global__ __launch_bounds__(kA_THREADS) void adjoint_tileA_kernel(AdjArgs a, int tiles_x)
+{
+    __shared__ double L[kA_LDS];
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int X0 = -1 + (int)(b % (unsigned)tiles_x) * kA_TX, Y0 = -1 + (int)(b / (unsigned)tiles_x) * kA_TY;
+    const int t = threadIdx.x;
+    tileA_states(a, X0, Y0, t, L);
+    __syncthreads();
+    tileA_faces(a, t, L);
+    __syncthreads();
+    tileA_fluxes(a, X0, Y0, t, L);
+}
+
+// Kernel B: a workgroup per tile of 64 x 8 virtual cells (a wavefront per
+// row), outputs its inner 62 x 6: the states of the tile and a ring into LDS,
+// per cell the face-state reverse pass from its FSb (its own share in
+// registers, the four to its neighbours in LDS), then per position everything
+// that lands on it, then per output the folded sum through W(U) plus lam'.
+// 155 KB of LDS.
+__global__ __launch_bounds__(kB_THREADS) void adjoint_tileB_kernel(AdjArgs a, int tiles_x)
+{
+    __shared__ double L[kB_LDS];
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int X0 = (int)(b % (unsigned)tiles_x) * kB_OX, Y0 = (int)(b / (unsigned)tiles_x) * kB_OY;
+    const int t = threadIdx.x;
+    tileB_states(a, X0, Y0, t, L);
+    __syncthreads();
+    const P self = tileB_shares(a, X0, Y0, t, L);
+    __syncthreads();
+    tileB_put_total(t, tileB_total(t, self, L), L);  // the totals go to a slot no thread reads here
+    __syncthreads();
+    tileB_gather(a, X0, Y0, t, L);
+}
+
 __global__ __launch_bounds__(256) void init_adjoint_kernel(const double* W, const double* lamU, double* lamW, int64_t n)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -99,6 +139,7 @@ __global__ __launch_bounds__(256) void init_adjoint_kernel(const double* W, cons
 size_t csh_adjoint_workspace_doubles(int nx, int ny)
 {
     const size_t ey = ny > 1 ? ny + 2 : 1, ne = (size_t)(nx + 2) * ey;
+    if (ny > 1) return ne * 6 * 4;  // the tiled pass: the face-state adjoints only
     return ne * 6 * (4 + 4 + 3) + (size_t)(nx + 4) * ey * 6;
 }
 
@@ -117,6 +158,7 @@ int csh_adjoint_impl(csh_grid_view v, double dt, const void* U, const void* lam_
     a.dx = v.dx;
     a.dy = v.dy;
     a.dt = dt;
+    set_step_factors(a);
     a.vc2 = v.vc * v.vc;
     a.rc2 = v.rc * v.rc;
     a.x0 = v.x0;
@@ -125,20 +167,20 @@ int csh_adjoint_impl(csh_grid_view v, double dt, const void* U, const void* lam_
     a.lam1 = static_cast<const double*>(lam_next);
     a.lam0 = static_cast<double*>(lam);
     const size_t ne = (size_t)a.ex * a.ey;
-    a.FS = ws;
-    a.FSb = ws + 24 * ne;
-    a.Cs = ws + 48 * ne;
-    a.XS = ws + 66 * ne;
-    const unsigned be = (unsigned)((ne + 255) / 256), bi = (unsigned)(((size_t)v.nx * v.ny + 255) / 256);
-    const long xs_waves = (long)((a.nx + 4 + kXsOwned - 1) / kXsOwned) * a.ey;
-    const unsigned bx = (unsigned)((xs_waves + 3) / 4);
     if (twod) {
-        adjoint_kernel<true, 1><<<be, 256, 0, s>>>(a);
-        adjoint_kernel<true, 2><<<be, 256, 0, s>>>(a);
-        adjoint_kernel<true, 3><<<be, 256, 0, s>>>(a);
-        adjoint_xsum_kernel<true><<<bx, 256, 0, s>>>(a);
-        adjoint_kernel<true, 4><<<bi, 256, 0, s>>>(a);
+        a.FSb = ws;
+        const int tax = (a.ex + kA_TX - 1) / kA_TX, tay = (a.ey + kA_TY - 1) / kA_TY;
+        const int tbx = (a.nx + kB_OX - 1) / kB_OX, tby = (a.ny + kB_OY - 1) / kB_OY;
+        adjoint_tileA_kernel<<<(unsigned)(tax * tay), kA_THREADS, 0, s>>>(a, tax);
+        adjoint_tileB_kernel<<<(unsigned)(tbx * tby), kB_THREADS, 0, s>>>(a, tbx);
     } else {
+        a.FS = ws;
+        a.FSb = ws + 24 * ne;
+        a.Cs = ws + 48 * ne;
+        a.XS = ws + 66 * ne;
+        const unsigned be = (unsigned)((ne + 255) / 256), bi = (unsigned)(((size_t)v.nx * v.ny + 255) / 256);
+        const long xs_waves = (long)((a.nx + 4 + kXsOwned - 1) / kXsOwned) * a.ey;
+        const unsigned bx = (unsigned)((xs_waves + 3) / 4);
         adjoint_kernel<false, 1><<<be, 256, 0, s>>>(a);
         adjoint_kernel<false, 2><<<be, 256, 0, s>>>(a);
         adjoint_xsum_kernel<false><<<bx, 256, 0, s>>>(a);

@@ -2,6 +2,7 @@
 // and the forward face/flux arithmetic in host loops, so the tests can check
 // the hand-written reverse pass against finite differences and the oracle's
 // dense Jacobian without a GPU.  Test infrastructure only.
+#include <algorithm>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -23,6 +24,7 @@ static AdjArgs make_args(int nx, int ny, int bcx, int bcy, double dx, double dy,
     a.dx = dx;
     a.dy = ny > 1 ? dy : 1.0;
     a.dt = dt;
+    set_step_factors(a);
     a.vc2 = vc * vc;
     a.rc2 = rc * rc;
     a.x0 = x0;
@@ -79,6 +81,47 @@ extern "C" int host_adjoint_step(int nx, int ny, int bcx, int bcy, double dx, do
     a.lam0 = lam0;
     if (ny > 1) adjoint_loops<true>(a);
     else adjoint_loops<false>(a);
+    return 0;
+}
+
+// The tiled two-kernel reverse pass of 2-D grids (kernels A and B) run on the
+// CPU: per tile, each phase for every thread, a host array standing for LDS;
+// the tiles in the GPU's numbering order.  NaN-filled buffers: a slot read
+// before it is written shows in the result.
+extern "C" int host_adjoint_step_tiled(int nx, int ny, int bcx, int bcy, double dx, double dy, double dt, double vc,
+                                       double rc, double x0, double y0, const double* U, const double* lam1,
+                                       double* lam0)
+{
+    if (ny < 2) return -1;
+    AdjArgs a = make_args(nx, ny, bcx, bcy, dx, dy, dt, vc, rc, x0, y0, U);
+    const size_t ne = (size_t)a.ex * a.ey;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    std::vector<double> fsb(24 * ne, nan);
+    a.FSb = fsb.data();
+    a.lam1 = lam1;
+    a.lam0 = lam0;
+    std::vector<double> L((size_t)(kA_LDS > kB_LDS ? kA_LDS : kB_LDS));
+    const int tax = (a.ex + kA_TX - 1) / kA_TX, tay = (a.ey + kA_TY - 1) / kA_TY;
+    for (int ty = 0; ty < tay; ++ty)
+        for (int tx = 0; tx < tax; ++tx) {
+            const int X0 = -1 + tx * kA_TX, Y0 = -1 + ty * kA_TY;
+            std::fill(L.begin(), L.end(), nan);
+            for (int t = 0; t < kA_THREADS; ++t) tileA_states(a, X0, Y0, t, L.data());
+            for (int t = 0; t < kA_THREADS; ++t) tileA_faces(a, t, L.data());
+            for (int t = 0; t < kA_THREADS; ++t) tileA_fluxes(a, X0, Y0, t, L.data());
+        }
+    const int tbx = (nx + kB_OX - 1) / kB_OX, tby = (ny + kB_OY - 1) / kB_OY;
+    std::vector<P> self(kB_THREADS), tot(kB_THREADS);
+    for (int ty = 0; ty < tby; ++ty)
+        for (int tx = 0; tx < tbx; ++tx) {
+            const int X0 = tx * kB_OX, Y0 = ty * kB_OY;
+            std::fill(L.begin(), L.end(), nan);
+            for (int t = 0; t < kB_THREADS; ++t) tileB_states(a, X0, Y0, t, L.data());
+            for (int t = 0; t < kB_THREADS; ++t) self[t] = tileB_shares(a, X0, Y0, t, L.data());
+            for (int t = 0; t < kB_THREADS; ++t) tot[t] = tileB_total(t, self[t], L.data());
+            for (int t = 0; t < kB_THREADS; ++t) tileB_put_total(t, tot[t], L.data());
+            for (int t = 0; t < kB_THREADS; ++t) tileB_gather(a, X0, Y0, t, L.data());
+        }
     return 0;
 }
 

@@ -26,6 +26,7 @@ def lib():
         L = ctypes.CDLL(build_host.build())
         sig = [ctypes.c_int] * 4 + [ctypes.c_double] * 7 + [_D, _D, _D]
         L.host_adjoint_step.argtypes = sig
+        L.host_adjoint_step_tiled.argtypes = sig
         L.host_step.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 7 + [_D, _D]
         L.host_init_adjoint.argtypes = [ctypes.c_int64, _D, _D, _D]
         L.host_xcd_block.argtypes = [ctypes.c_uint, ctypes.c_uint]
@@ -52,6 +53,14 @@ def host_step(g, dt, U):
 def host_adjoint(g, dt, U, lam):
     out = np.empty_like(U)
     lib().host_adjoint_step(*geo(g), dt, g.vc, g.rc, g.x0, g.y0, p(U), p(np.ascontiguousarray(lam)), p(out))
+    return out
+
+
+def host_adjoint_tiled(g, dt, U, lam):
+    """The tiled two-kernel reverse pass (2-D) run on the CPU."""
+    out = np.empty_like(U)
+    assert lib().host_adjoint_step_tiled(*geo(g), dt, g.vc, g.rc, g.x0, g.y0, p(U), p(np.ascontiguousarray(lam)),
+                                         p(out)) == 0
     return out
 
 
@@ -150,3 +159,25 @@ def test_xcd_renumbering_is_a_bijection(nb):
     for x in range(8):
         mine = sorted(logical[b] for b in range(x, nb, 8))
         assert mine == list(range(mine[0], mine[0] + len(mine))) if mine else True
+
+
+# grids around the tiles of the two-kernel reverse pass (A: 32 x 8 extended
+# cells; B: 62 x 6 outputs) and tiny ones; every boundary combination
+@pytest.mark.parametrize("shape", [(2, 2), (3, 5), (7, 3), (61, 6), (62, 7), (63, 13), (124, 12), (125, 31), (30, 9)])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
+def test_tiled_reverse_pass_equals_five_stage_pass(shape, bc):
+    """The tiled reverse pass (wrap on periodic axes, folded ghost positions on
+    outflow ones) against the five-stage pass on the extended grid: the same
+    transpose, summed in another order."""
+    nx, ny = shape
+    w = wl.periodic(max(64, nx + 8, ny + 8), 53)
+    W = np.ascontiguousarray(w.W[:, 3:3 + ny, 4:4 + nx])
+    W[1:3] *= 2.0
+    g = oracle.Grid(nx, ny, 1.0 / nx, 1.3 / ny, bc[0], bc[1], -0.45, -0.5, 0.7 if bc[0] else 0.0, 0.15)
+    U = oracle.cons_field(W)
+    dt = 0.8 / oracle.max_signal_speed(g, U)
+    lam = np.random.default_rng(nx * 100 + ny).standard_normal(U.shape)
+    ref = host_adjoint(g, dt, U, lam)
+    got = host_adjoint_tiled(g, dt, U, lam)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() / np.abs(ref).max() < 1e-12
