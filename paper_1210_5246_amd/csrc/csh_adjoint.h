@@ -695,7 +695,7 @@ constexpr int kA_TX = 32, kA_TY = 8, kA_THREADS = kA_TX * kA_TY;
 constexpr int kA_WX = kA_TX + 3, kA_WY = kA_TY + 3;  // states: cells [X0 - 1, X0 + TX + 2)
 constexpr int kA_FX = kA_TX + 1, kA_FY = kA_TY + 1;  // face states: cells [X0, X0 + TX + 1)
 constexpr int kA_NW = kA_WX * kA_WY, kA_NF = kA_FX * kA_FY;
-constexpr int kA_LDS = 6 * kA_NW + 24 * kA_NF;       // doubles of LDS
+constexpr int kA_LDS = 6 * kA_NW + 12 * kA_NF;       // doubles of LDS: states, low x and y face states
 
 // kernel B: a tile of kB_W x kB_H virtual cells (one wavefront per row), the
 // outputs its inner (kB_W - 2) x (kB_H - 2) cells
@@ -741,30 +741,46 @@ CSH_HD void tileA_states(const AdjArgs& a, int X0, int Y0, int t, double* L)
     }
 }
 
-// A2: face states of the cells [X0, X0 + TX + 1) x [Y0, Y0 + TY + 1)
-CSH_HD void tileA_faces(const AdjArgs& a, int t, double* L)
+// face states of cell k of the face-state block [X0, X0 + TX + 1) x [Y0, Y0 + TY + 1)
+CSH_HD Faces<double> tileA_face_states(const AdjArgs& a, int k, const double* L)
 {
-    double* F = L + 6 * kA_NW;
-    for (int k = t; k < kA_NF; k += kA_THREADS) {
-        const int lx = k % kA_FX + 1, ly = k / kA_FX + 1;  // position in the state block
-        const int c = ly * kA_WX + lx;
-        const P W0 = lds_get(L, kA_NW, 0, c);
-        const Faces<double> f = face_states<double, true>(W0, rcp(W0.r), lds_get(L, kA_NW, 0, c - 1),
-                                                          lds_get(L, kA_NW, 0, c + 1), lds_get(L, kA_NW, 0, c - kA_WX),
-                                                          lds_get(L, kA_NW, 0, c + kA_WX), a.kx, a.ky);
-        lds_put(F, kA_NF, XHI * 6 * kA_NF, k, f.xhi);
-        lds_put(F, kA_NF, XLO * 6 * kA_NF, k, f.xlo);
-        lds_put(F, kA_NF, YHI * 6 * kA_NF, k, f.yhi);
-        lds_put(F, kA_NF, YLO * 6 * kA_NF, k, f.ylo);
+    const int lx = k % kA_FX + 1, ly = k / kA_FX + 1;  // position in the state block
+    const int c = ly * kA_WX + lx;
+    const P W0 = lds_get(L, kA_NW, 0, c);
+    return face_states<double, true>(W0, rcp(W0.r), lds_get(L, kA_NW, 0, c - 1), lds_get(L, kA_NW, 0, c + 1),
+                                     lds_get(L, kA_NW, 0, c - kA_WX), lds_get(L, kA_NW, 0, c + kA_WX), a.kx, a.ky);
+}
+
+// A2: the face states of the thread's own cell e = (X0 + t % TX, Y0 + t / TX):
+// the high ones kept (returned), the low ones written to LDS for the faces of
+// the cells to the left and below; then the low x face states of the column
+// to the right of the tile and the low y face states of the row above it
+CSH_HD void tileA_faces(const AdjArgs& a, int t, double* L, P& xhi, P& yhi)
+{
+    double* X = L + 6 * kA_NW;
+    double* Y = X + 6 * kA_NF;
+    const int k = (t / kA_TX) * kA_FX + t % kA_TX;
+    const Faces<double> f = tileA_face_states(a, k, L);
+    xhi = f.xhi;
+    yhi = f.yhi;
+    lds_put(X, kA_NF, 0, k, f.xlo);
+    lds_put(Y, kA_NF, 0, k, f.ylo);
+    if (t < kA_TY + kA_TX) {
+        const bool col = t < kA_TY;  // the column x = X0 + TX, else the row y = Y0 + TY
+        const int k2 = col ? t * kA_FX + kA_TX : kA_TY * kA_FX + (t - kA_TY);
+        const Faces<double> g = tileA_face_states(a, k2, L);
+        if (col) lds_put(X, kA_NF, 0, k2, g.xlo);
+        else lds_put(Y, kA_NF, 0, k2, g.ylo);
     }
 }
 
-// A3: the extended cell e = (X0 + t % TX, Y0 + t / TX): the flux adjoints of its
-// high x and y faces, through HLL into the adjoints of the two face states of
-// each (written to FSb); the slots of the ring that no face writes are cleared
-CSH_HD void tileA_fluxes(const AdjArgs& a, int X0, int Y0, int t, const double* L)
+// A3: the extended cell e of the thread: the flux adjoints of its high x and
+// y faces, through HLL into the adjoints of the two face states of each
+// (written to FSb); the slots of the ring that no face writes are cleared
+CSH_HD void tileA_fluxes(const AdjArgs& a, int X0, int Y0, int t, const double* L, const P& xhi, const P& yhi)
 {
-    const double* F = L + 6 * kA_NW;
+    const double* X = L + 6 * kA_NW;
+    const double* Y = X + 6 * kA_NF;
     const int i = X0 + t % kA_TX, j = Y0 + t / kA_TX;
     if (i > a.nx || j > a.ny) return;  // outside the extended grid
     const size_t ne = (size_t)a.ex * a.ey, e = ext_index(a, i, j);
@@ -778,15 +794,14 @@ CSH_HD void tileA_fluxes(const AdjArgs& a, int X0, int Y0, int t, const double* 
     if (i <= a.nx - 1) {  // x face i + 1/2
         const C Fb = csub(lam_prime_virtual(a, i + 1, j), l0, a.cx);
         P wlb = zero_p(), wrb = zero_p();
-        hll_vjp(lds_get(F, kA_NF, XHI * 6 * kA_NF, k), lds_get(F, kA_NF, XLO * 6 * kA_NF, k + 1), Fb, wlb, wrb);
+        hll_vjp(xhi, lds_get(X, kA_NF, 0, k + 1), Fb, wlb, wrb);
         store_p(a.FSb, ne, XHI, e, wlb);
         store_p(a.FSb, ne, XLO, e + 1, wrb);
     }
     if (j <= a.ny - 1) {  // y face j + 1/2
         const C Gb = csub(lam_prime_virtual(a, i, j + 1), l0, a.cy);
         P wlb = zero_p(), wrb = zero_p();
-        hll_vjp(swap(lds_get(F, kA_NF, YHI * 6 * kA_NF, k)), swap(lds_get(F, kA_NF, YLO * 6 * kA_NF, k + kA_FX)),
-                swap(Gb), wlb, wrb);
+        hll_vjp(swap(yhi), swap(lds_get(Y, kA_NF, 0, k + kA_FX)), swap(Gb), wlb, wrb);
         store_p(a.FSb, ne, YHI, e, swapb(wlb));
         store_p(a.FSb, ne, YLO, e + a.ex, swapb(wrb));
     }
@@ -817,10 +832,18 @@ CSH_HD void tileB_states(const AdjArgs& a, int X0, int Y0, int t, double* L)
     }
 }
 
+// the face-state adjoints of the thread's cell; zero beyond the ring
+CSH_HD Faces<double> tileB_face_adjoints(const AdjArgs& a, int X0, int Y0, int t)
+{
+    const long e = ext_of_virtual(a, X0 - 1 + t % kB_W, Y0 - 1 + t / kB_W);
+    if (e < 0) return {zero_p(), zero_p(), zero_p(), zero_p()};
+    return load_face_adjoints(a, (size_t)a.ex * a.ey, (size_t)e, true);
+}
+
 // B1: the face-state reverse pass of the virtual cell at lane l, row w of the
-// tile (X0 - 1 + l, Y0 - 1 + w): its own share returned, the four it gives its
-// neighbours written to LDS
-CSH_HD P tileB_shares(const AdjArgs& a, int X0, int Y0, int t, double* L)
+// tile (X0 - 1 + l, Y0 - 1 + w) from its face-state adjoints fb: its own share
+// returned, the four it gives its neighbours written to LDS
+CSH_HD P tileB_shares(const AdjArgs& a, int X0, int Y0, int t, double* L, const Faces<double>& fb)
 {
     const double* S = L + 5 * 6 * kB_THREADS;
     const int l = t % kB_W, w = t / kB_W;
@@ -830,12 +853,7 @@ CSH_HD P tileB_shares(const AdjArgs& a, int X0, int Y0, int t, double* L)
     const long e = ext_of_virtual(a, i, j);
     // the y part first, its two neighbour shares stored before the x part
     // starts (fewer values live at once)
-    Faces<double> fb{zero_p(), zero_p(), zero_p(), zero_p()};
-    P W0 = zero_p();
-    if (e >= 0) {
-        fb = load_face_adjoints(a, (size_t)a.ex * a.ey, (size_t)e, true);
-        W0 = lds_get(S, kB_NS, 0, c);
-    }
+    const P W0 = e >= 0 ? lds_get(S, kB_NS, 0, c) : zero_p();
     {
         P bm = zero_p(), bp = zero_p();
         if (e >= 0)

@@ -1,32 +1,35 @@
 // Adjoint of one sweep at frozen timestep (FP64): lam^n = (d S_dt / d U^n)^T lam^{n+1}.
 //
-// The forward step reads primitive states at "extended" cells e = (i, j),
-// i in [-1, nx], j in [-1, ny] (2-D), whose values come from the mapped cells
-// map(e) of the boundary conditions; each extended cell builds its four face
-// states from itself and its four neighbours; every face flux uses the high
-// state of one extended cell and the low state of the next; the update of an
-// interior cell uses its four faces.  The reverse pass follows the same
-// structure in four steps (five kernels: the third runs as two), with fixed
-// slots instead of atomics so the result is deterministic:
+// 2-D grids: two LDS-tiled kernels (adjoint_tileA_kernel, adjoint_tileB_kernel,
+// the phase bodies in csh_adjoint.h): A recomputes the face states of a tile
+// and takes the flux adjoints of its faces through HLL into the face-state
+// adjoints, B takes those through the face-state reverse pass, sums the shares
+// that land on each cell and folds the ghost positions of outflow axes.
+//
+// 1-D grids: the forward step reads primitive states at "extended" cells
+// e = i, i in [-1, nx], whose values come from the mapped cells map(e) of the
+// boundary conditions; each extended cell builds its face states from itself
+// and its two neighbours; every face flux uses the high state of one extended
+// cell and the low state of the next.  The reverse pass follows the same
+// structure in four kernels, with fixed slots instead of atomics so the result
+// is deterministic:
 //   1. faces:  recompute the face states of every extended cell -> FS
 //   2. hll:    per face, lam' = K^T lam^{n+1} (kick), flux adjoint
 //              dt/dx (lam'_{i+1} - lam'_i), HLL vjp -> adjoints of the two face
 //              states, each written to its one slot in FSb
-//   3. cells:  per extended cell, the vjp of its face-state computation gives
-//              the adjoints of its five input primitive states; in two
-//              kernels, which halves the live state of each: the y part ->
-//              slots C[self, down, up], then the x part (adds to self; left,
-//              right shares), whose wavefronts each cover 64 consecutive
-//              cells of a row and sum self + the right neighbour's left share
-//              + the left neighbour's right share by lane shifts into one
-//              value per padded position (XS) for the 62 inner lanes
-//   4. gather: per interior cell, sum XS and the down / up slots that land on
-//              each padded position, fold the padded positions that the
-//              boundary mapping sends to this cell, chain through W(U) and
-//              add lam' itself.
+//   3. cells:  per extended cell, the vjp of its face-state computation; a
+//              wavefront covers 64 consecutive cells and sums self + the right
+//              neighbour's left share + the left neighbour's right share by
+//              lane shifts into one value per padded position (XS)
+//   4. gather: per interior cell, sum the XS of the padded positions that the
+//              boundary mapping sends to this cell, chain through W(U) and add
+//              lam' itself.
+// (The 2-D grids ran this scheme with a y part as five kernels before the
+// tiled pass replaced it; its per-cell bodies remain the reference the tiled
+// pass is tested against on the CPU.)
 //
-// The kernels take their workgroup numbers XCD-aware (xcd_block), so the rows
-// a thread reads from its y neighbours sit in the same L2.
+// The kernels take their workgroup numbers XCD-aware (xcd_block), so tiles or
+// rows that share halo cells sit in the same L2.
 #include <string>
 
 #include "csh_adjoint.h"
@@ -82,9 +85,11 @@ __global__ __launch_bounds__(256) void adjoint_xsum_kernel(AdjArgs a)
 
 // The tiled reverse pass of 2-D grids.  Kernel A: a workgroup per tile of
 // 32 x 8 extended cells (one thread each): the states of the tile and a
-// ring into LDS, the face states of the tile plus one column and one row,
-// then per cell the flux adjoints of its high x and y faces through HLL into
-// the face-state adjoints (FSb, device memory).  75.5 KB of LDS.
+// ring into LDS, the face states of each cell (its high ones kept in
+// registers, its low ones shared through LDS, plus the low ones of the column
+// to the right and the row above), then per cell the flux adjoints of its
+// high x and y faces through HLL into the face-state adjoints (FSb, device
+// memory).  47 KB of LDS: three workgroups per CU.
 __global__ __launch_bounds__(kA_THREADS) void adjoint_tileA_kernel(AdjArgs a, int tiles_x)
 {
     __shared__ double L[kA_LDS];
@@ -93,9 +98,10 @@ __global__ __launch_bounds__(kA_THREADS) void adjoint_tileA_kernel(AdjArgs a, in
     const int t = threadIdx.x;
     tileA_states(a, X0, Y0, t, L);
     __syncthreads();
-    tileA_faces(a, t, L);
+    P xhi, yhi;
+    tileA_faces(a, t, L, xhi, yhi);
     __syncthreads();
-    tileA_fluxes(a, X0, Y0, t, L);
+    tileA_fluxes(a, X0, Y0, t, L, xhi, yhi);
 }
 
 // Kernel B: a workgroup per tile of 64 x 8 virtual cells (a wavefront per
@@ -112,7 +118,8 @@ __global__ __launch_bounds__(kB_THREADS) void adjoint_tileB_kernel(AdjArgs a, in
     const int t = threadIdx.x;
     tileB_states(a, X0, Y0, t, L);
     __syncthreads();
-    const P self = tileB_shares(a, X0, Y0, t, L);
+    // (loading the face-state adjoints before the staging above measured slower)
+    const P self = tileB_shares(a, X0, Y0, t, L, tileB_face_adjoints(a, X0, Y0, t));
     __syncthreads();
     tileB_put_total(t, tileB_total(t, self, L), L);  // the totals go to a slot no thread reads here
     __syncthreads();

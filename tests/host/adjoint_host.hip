@@ -102,22 +102,27 @@ extern "C" int host_adjoint_step_tiled(int nx, int ny, int bcx, int bcy, double 
     a.lam0 = lam0;
     std::vector<double> L((size_t)(kA_LDS > kB_LDS ? kA_LDS : kB_LDS));
     const int tax = (a.ex + kA_TX - 1) / kA_TX, tay = (a.ey + kA_TY - 1) / kA_TY;
+    std::vector<P> xhi(kA_THREADS), yhi(kA_THREADS);
     for (int ty = 0; ty < tay; ++ty)
         for (int tx = 0; tx < tax; ++tx) {
             const int X0 = -1 + tx * kA_TX, Y0 = -1 + ty * kA_TY;
             std::fill(L.begin(), L.end(), nan);
             for (int t = 0; t < kA_THREADS; ++t) tileA_states(a, X0, Y0, t, L.data());
-            for (int t = 0; t < kA_THREADS; ++t) tileA_faces(a, t, L.data());
-            for (int t = 0; t < kA_THREADS; ++t) tileA_fluxes(a, X0, Y0, t, L.data());
+            for (int t = 0; t < kA_THREADS; ++t) tileA_faces(a, t, L.data(), xhi[t], yhi[t]);
+            for (int t = 0; t < kA_THREADS; ++t) tileA_fluxes(a, X0, Y0, t, L.data(), xhi[t], yhi[t]);
         }
     const int tbx = (nx + kB_OX - 1) / kB_OX, tby = (ny + kB_OY - 1) / kB_OY;
     std::vector<P> self(kB_THREADS), tot(kB_THREADS);
+    std::vector<Faces<double>> fbs(kB_THREADS);
     for (int ty = 0; ty < tby; ++ty)
         for (int tx = 0; tx < tbx; ++tx) {
             const int X0 = tx * kB_OX, Y0 = ty * kB_OY;
             std::fill(L.begin(), L.end(), nan);
-            for (int t = 0; t < kB_THREADS; ++t) tileB_states(a, X0, Y0, t, L.data());
-            for (int t = 0; t < kB_THREADS; ++t) self[t] = tileB_shares(a, X0, Y0, t, L.data());
+            for (int t = 0; t < kB_THREADS; ++t) {
+                fbs[t] = tileB_face_adjoints(a, X0, Y0, t);
+                tileB_states(a, X0, Y0, t, L.data());
+            }
+            for (int t = 0; t < kB_THREADS; ++t) self[t] = tileB_shares(a, X0, Y0, t, L.data(), fbs[t]);
             for (int t = 0; t < kB_THREADS; ++t) tot[t] = tileB_total(t, self[t], L.data());
             for (int t = 0; t < kB_THREADS; ++t) tileB_put_total(t, tot[t], L.data());
             for (int t = 0; t < kB_THREADS; ++t) tileB_gather(a, X0, Y0, t, L.data());
