@@ -285,6 +285,12 @@ int csh_batch_run(csh_batch *b, int nsteps, double cfl, void *U, void *U_work, d
  * Time the candidate workgroup sizes on this device for this batch (a few
  * steps each, on scratch copies of U; U is not modified), keep the fastest
  * as the batch's default and write it to *best_threads.  Synchronises.
+ * The choice is persisted: one line "<key> <threads>" per batch shape in the
+ * file CSH_TUNE_CACHE names (the value "off" disables it; default
+ * $HOME/.cache/cshydro/batch_autotune.txt), with key
+ * "arch=<gcnArchName>;cus=<compute units>;tubes=<ntubes>;cells=<total cells>;maxlen=<longest tube>";
+ * a later call for the same shape on the same kind of device takes the
+ * recorded size without probing (the last record of a key wins).
  */
 int csh_batch_autotune(csh_batch *b, int probe_steps, double cfl, const void *U, int *best_threads);
 

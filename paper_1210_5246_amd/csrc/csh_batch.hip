@@ -9,8 +9,12 @@
 // the work buffer; a workgroup barrier separates them.  No host round trip,
 // no grid-wide barrier: tubes never interact.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
 #include <numeric>
 #include <string>
+#include <sys/stat.h>
 #include <vector>
 
 #include "csh_api_util.h"
@@ -154,6 +158,7 @@ struct csh_batch {
     int* counter = nullptr;
     int* flag = nullptr;
     int best_threads = 256;
+    int max_len = 0;
     hipGraphExec_t exec = nullptr;
     int g_nsteps = -1, g_threads = 0;
     double g_cfl = 0;
@@ -212,6 +217,7 @@ extern "C" int csh_batch_init(csh_batch** out, int ntubes, const int64_t* offset
     csh_batch* b = new csh_batch;
     b->ntubes = ntubes;
     b->N = offsets[ntubes];
+    b->max_len = *std::max_element(len.begin(), len.end());
     b->stream = static_cast<hipStream_t>(stream);
     auto cleanup = [&](int code) {
         csh_batch_destroy(b);
@@ -276,10 +282,72 @@ extern "C" int csh_batch_run(csh_batch* b, int nsteps, double cfl, void* U, void
     return CSH_OK;
 }
 
+namespace {
+
+// ---- persisted choices of the autotuner --------------------------------------------------------
+//
+// One line per tuned batch shape, "<key> <threads>", key =
+// "arch=<gcnArchName>;cus=<compute units>;tubes=<ntubes>;cells=<total cells>;maxlen=<longest tube>".
+// The file is CSH_TUNE_CACHE if set ("off" disables the cache), else
+// $HOME/.cache/cshydro/batch_autotune.txt.  Unreadable or malformed lines are
+// ignored; a failed write loses nothing but the record.
+
+std::string tune_cache_path()
+{
+    if (const char* e = std::getenv("CSH_TUNE_CACHE")) return std::string(e) == "off" ? std::string() : std::string(e);
+    const char* home = std::getenv("HOME");
+    if (!home || !*home) return std::string();
+    const std::string dir = std::string(home) + "/.cache/cshydro";
+    (void)mkdir((std::string(home) + "/.cache").c_str(), 0755);
+    (void)mkdir(dir.c_str(), 0755);
+    return dir + "/batch_autotune.txt";
+}
+
+std::string tune_key(const csh_batch* b)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "arch=%s;cus=%d;tubes=%d;cells=%lld;maxlen=%d", prop.gcnArchName,
+                  prop.multiProcessorCount, b->ntubes, (long long)b->N, b->max_len);
+    return std::string(buf);
+}
+
+int tune_lookup(const std::string& path, const std::string& key)
+{
+    if (path.empty() || key.empty()) return 0;
+    std::ifstream f(path);
+    std::string line;
+    int found = 0;
+    while (std::getline(f, line)) {
+        if (line.size() > key.size() && line.compare(0, key.size(), key) == 0 && line[key.size()] == ' ') {
+            const int t = std::atoi(line.c_str() + key.size() + 1);
+            if (valid_threads(t)) found = t;  // the last record wins
+        }
+    }
+    return found;
+}
+
+void tune_record(const std::string& path, const std::string& key, int threads)
+{
+    if (path.empty() || key.empty()) return;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << ' ' << threads << '\n';
+}
+
+}  // namespace
+
 extern "C" int csh_batch_autotune(csh_batch* b, int probe_steps, double cfl, const void* U, int* best_threads)
 {
     if (!b || !U || !best_threads) return csh_fail(CSH_ERR_ARG, "NULL argument");
     if (probe_steps < 1 || !(cfl > 0)) return csh_fail(CSH_ERR_ARG, "probe_steps >= 1 and cfl > 0 required");
+    const std::string path = tune_cache_path(), key = tune_key(b);
+    if (const int cached = tune_lookup(path, key)) {
+        b->best_threads = cached;
+        *best_threads = cached;
+        return CSH_OK;
+    }
     const size_t bytes = sizeof(double) * 6 * (size_t)b->N;
     double *A = nullptr, *B = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -321,6 +389,7 @@ extern "C" int csh_batch_autotune(csh_batch* b, int probe_steps, double cfl, con
     release();
     b->best_threads = best;
     *best_threads = best;
+    tune_record(path, key, best);
     return CSH_OK;
 }
 

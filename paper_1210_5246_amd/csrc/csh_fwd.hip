@@ -213,21 +213,32 @@ hipError_t launch_init(const T* W, T* U, int64_t n, int* flag, hipStream_t s)
 
 // ---- standalone CFL-rate reduction ----------------------------------------------------------------
 
+// Two cells per thread and iteration (their loads issued together), a
+// workgroup maximum in LDS and one 64-bit atomic per workgroup (a wavefront's
+// atomic on the one slot serialises with every other's).
 template <typename T>
 __global__ __launch_bounds__(256) void maxspeed_kernel(const T* __restrict__ U, int64_t n, int twod,
                                                        double idx, double idy, Slot* slot, int* flag)
 {
     double s = 0.0;
     bool bad = false;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const Prim<T> w = to_prim(load_cons(U, (size_t)n, (size_t)c));
-        s = fmax(s, twod ? signal_rate<T, true>(w, idx, idy) : signal_rate<T, false>(w, idx, idy));
-        bad = bad || !physical(w);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += 2 * stride) {
+        const int64_t c2 = c + stride;
+        const Cons<T> ua = load_cons(U, (size_t)n, (size_t)c);
+        const Cons<T> ub = load_cons(U, (size_t)n, (size_t)(c2 < n ? c2 : c));
+        const Prim<T> wa = to_prim(ua), wb = to_prim(ub);
+        s = fmax(s, twod ? signal_rate<T, true>(wa, idx, idy) : signal_rate<T, false>(wa, idx, idy));
+        s = fmax(s, twod ? signal_rate<T, true>(wb, idx, idy) : signal_rate<T, false>(wb, idx, idy));
+        bad = bad || !physical(wa) || !physical(wb);
     }
     s = wave_max(s);
-    if ((threadIdx.x & 63) == 0) atomic_max_pos(&slot->s_bits, s);
-    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = s;
+    if (__any(bad) && lane == 0) atomicOr(flag, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) atomic_max_pos(&slot->s_bits, fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
 }
 
 template <typename T>
@@ -235,7 +246,7 @@ hipError_t launch_maxspeed(const T* U, int nx, int ny, double dx, double dy, Slo
                            hipStream_t s)
 {
     const int64_t n = (int64_t)nx * ny;
-    int64_t blocks = (n + 255) / 256;
+    int64_t blocks = (n + 511) / 512;
     if (blocks > 4096) blocks = 4096;
     maxspeed_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(U, n, ny > 1, 1.0 / dx,
                                                                     ny > 1 ? 1.0 / dy : 0.0, slot, flag);

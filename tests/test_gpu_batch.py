@@ -80,7 +80,8 @@ def test_batch_edge_lengths_and_odd_steps():
         assert max_rel_error(U[:, offsets[k]:offsets[k + 1]], ref) <= 1e-11, int(lengths[k])
 
 
-def test_thread_counts_agree_bitwise_and_autotune():
+def test_thread_counts_agree_bitwise_and_autotune(monkeypatch):
+    monkeypatch.setenv("CSH_TUNE_CACHE", "off")   # probe, whatever a cache holds
     t = wl.tubes(ntubes=64, seed=41)
     say("thread counts bitwise, autotune")
     W = torch.from_numpy(t.W).to(DEV)
@@ -98,6 +99,37 @@ def test_thread_counts_agree_bitwise_and_autotune():
     assert torch.equal(b.U, U0)          # tuning works on scratch copies
     b.run(20, 0.8)                        # default = tuned size
     assert torch.equal(b.U, outs[0][0])
+
+
+def test_autotune_persists_its_choice(tmp_path, monkeypatch):
+    """The tuned workgroup size is recorded per batch shape and device kind;
+    a later handle of the same shape takes the record without probing."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("CSH_TUNE_CACHE", str(cache))
+    t = wl.tubes(ntubes=64, seed=41)
+    say("autotune cache")
+    W = torch.from_numpy(t.W).to(DEV)
+    best = csh.Batch(W, t.offsets).autotune(probe_steps=4)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    key, th = lines[0].rsplit(" ", 1)
+    assert int(th) == best
+    props = torch.cuda.get_device_properties(0)
+    assert f"cus={props.multi_processor_count};" in key and ";tubes=64;" in key
+    assert f";cells={int(t.offsets[-1])};" in key and key.endswith(f";maxlen={int(t.lengths.max())}")
+    # a record for this key that the probe need not pick is taken as it stands
+    other = 64 if best != 64 else 128
+    cache.write_text(f"{key} {other}\n")
+    assert csh.Batch(W, t.offsets).autotune(probe_steps=4) == other
+    assert cache.read_text().splitlines() == [f"{key} {other}"]   # a hit records nothing
+    # another shape misses and is recorded beside it
+    t2 = subset(t, list(range(10)))
+    best2 = csh.Batch(torch.from_numpy(t2.W).to(DEV), t2.offsets).autotune(probe_steps=4)
+    assert cache.read_text().splitlines()[1].endswith(f" {best2}")
+    # switched off: probes, records nothing
+    monkeypatch.setenv("CSH_TUNE_CACHE", "off")
+    assert csh.Batch(W, t.offsets).autotune(probe_steps=4) in (64, 128, 256, 512, 1024)
+    assert len(cache.read_text().splitlines()) == 2
 
 
 def test_batch_equals_plain_path_per_tube():
