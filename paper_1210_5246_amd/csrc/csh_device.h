@@ -35,12 +35,24 @@ namespace csh {
 // one Newton step.  gfx950's FP64 v_rcp/v_rsq are accurate to ~5e-8 relative;
 // one step brings them to ~4e-15, well inside the scheme's parity tolerance,
 // at about half the instructions of the IEEE-exact sequences.  FP32 uses the
-// single-precision instructions (~1 ulp).  On the host (tests) they are exact.
+// single-precision instructions (~1 ulp).  On the host (tests) they are exact;
+// the refinement steps themselves are host-callable, so the tests run them
+// from approximations with the hardware's error.
+//   r' = r + r (1 - x r)            (relative error e -> e^2)
+CSH_HD double rcp_refine(double x, double r) { return fma(fma(-x, r, 1.0), r, r); }
+//   y' = y + (y / 2)(1 - x y^2)     (e -> 3/2 e^2)
+CSH_HD double rsqrt_refine(double x, double y) { return fma(0.5 * y, fma(-x * y, y, 1.0), y); }
+//   s = x y, s' = s + (s / 2)(1 - s y)   (the square root from y ~ 1/sqrt(x))
+CSH_HD double sqrt_refine(double x, double y)
+{
+    const double s = x * y;
+    return fma(0.5 * s, fma(-s, y, 1.0), s);
+}
+
 CSH_HD double rcp(double x)
 {
 #ifdef __HIP_DEVICE_COMPILE__
-    const double r = __builtin_amdgcn_rcp(x);
-    return fma(fma(-x, r, 1.0), r, r);
+    return rcp_refine(x, __builtin_amdgcn_rcp(x));
 #else
     return 1.0 / x;
 #endif
@@ -56,8 +68,7 @@ CSH_HD float rcp(float x)
 CSH_HD double rsqrt(double x)
 {
 #ifdef __HIP_DEVICE_COMPILE__
-    const double y = __builtin_amdgcn_rsq(x);
-    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return rsqrt_refine(x, __builtin_amdgcn_rsq(x));
 #else
     return 1.0 / sqrt(x);
 #endif
@@ -73,15 +84,13 @@ CSH_HD float rsqrt(float x)
 
 // Square root of a positive number: on the device s0 = x rsq(x) from the
 // hardware approximation, then one Newton step of the square root written
-// with the same reciprocal root, s = s0 + (s0 / 2)(1 - s0 y0) (~4e-15, one
-// instruction fewer than refining the reciprocal root and multiplying by x).
-// NaN for x <= 0 (as x rsqrt(x)).
+// with the same reciprocal root (sqrt_refine; ~4e-15, one instruction fewer
+// than refining the reciprocal root and multiplying by x).  NaN for x <= 0
+// (as x rsqrt(x)).
 CSH_HD double sqrt_pos(double x)
 {
 #ifdef __HIP_DEVICE_COMPILE__
-    const double y = __builtin_amdgcn_rsq(x);
-    const double s = x * y;
-    return fma(0.5 * s, fma(-s, y, 1.0), s);
+    return sqrt_refine(x, __builtin_amdgcn_rsq(x));
 #else
     return x * (1.0 / sqrt(x));
 #endif

@@ -99,3 +99,9 @@ extern "C" void dev_hll3(int axis, const double* wl, const double* wr, double* o
     else if (axis == 1) hll3<1>(wl, wr, out);
     else hll3<2>(wl, wr, out);
 }
+
+// the Newton refinements of the device's reciprocal, reciprocal square root and
+// square root, fed an approximation from the caller
+extern "C" double dev_rcp_refine(double x, double r) { return rcp_refine(x, r); }
+extern "C" double dev_rsqrt_refine(double x, double y) { return rsqrt_refine(x, y); }
+extern "C" double dev_sqrt_refine(double x, double y) { return sqrt_refine(x, y); }

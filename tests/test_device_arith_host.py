@@ -161,3 +161,43 @@ def test_hll_3d(axis):
         ref = oracle.hll3(axis, wl[k], wr[k])
         scale = max(np.abs(oracle.flux3(axis, oracle.cons3(w))).max() for w in (wl[k], wr[k]))
         assert close(got, ref, scale, 1e-13), (k, got, ref)
+
+
+# ---- the device's reciprocal and square roots ------------------------------------------------
+
+def _exact(fn, x):
+    """fn(x) rounded from an exact rational (or a double-double square root)."""
+    from fractions import Fraction
+    import decimal
+    if fn == "rcp":
+        return Fraction(1) / Fraction(x)
+    ctx = decimal.Context(prec=60)
+    r = decimal.Decimal(x).sqrt(ctx)
+    return Fraction(r) if fn == "sqrt" else Fraction(1) / Fraction(r)
+
+
+@pytest.mark.parametrize("fn,bound", [("rcp", 4e-15), ("rsqrt", 6e-15), ("sqrt", 6e-15)])
+def test_newton_refinement_from_hardware_accuracy(fn, bound):
+    """On the GPU the reciprocal and square roots are the hardware's FP64
+    approximation (measured ~5e-8 relative on gfx950) refined by one Newton
+    step.  The refinement code itself, run here from approximations 6e-8 off
+    in either direction (and at random within that), lands within the bound on
+    x across 1e-200..1e200: the error squares (x 3/2 for the roots), plus the
+    step's own rounding."""
+    from fractions import Fraction
+    f = {"rcp": lib().dev_rcp_refine, "rsqrt": lib().dev_rsqrt_refine, "sqrt": lib().dev_sqrt_refine}[fn]
+    f.argtypes = [ctypes.c_double, ctypes.c_double]
+    f.restype = ctypes.c_double
+    r = np.random.default_rng(77)
+    xs = np.concatenate([10.0 ** r.uniform(-200, 200, 300), r.uniform(0.5, 2.0, 300), [1.0, 3.0, 0.1, 1e-300 * 1e100]])
+    worst = 0.0
+    for x in xs:
+        x = float(x)
+        # the approximation the refinement starts from: of 1/x for rcp, of 1/sqrt(x) for both roots
+        target = _exact("rcp", x) if fn == "rcp" else _exact("rsqrt", x)
+        for e in (6e-8, -6e-8, float(r.uniform(-6e-8, 6e-8))):
+            approx = float(target * (1 + Fraction(e)))
+            got = Fraction(f(x, approx))
+            want = _exact(fn, x)
+            worst = max(worst, float(abs(got - want) / want))
+    assert worst <= bound, worst
