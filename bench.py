@@ -27,10 +27,10 @@ BYTES_PER_CELL_F32 = 48
 BYTES_PER_CELL_KT_F64 = 96
 KT_CFL = 0.8
 # 3-D: 10 planes read + 10 written = 160 B per cell-update for a single pass;
-# the z-march also writes the two y-face states (160 B) and the partial update
-# (80 B), which the second kernel reads back: 640 B
+# a workgroup reads the rows j0 - 2 .. j0 + 3 for its two output rows, so each
+# row is read by three workgroups (240 B) unless the cache serves it: 320 B
 BYTES_PER_CELL_3D_MIN = 160
-BYTES_PER_CELL_3D_DESIGN = 640
+BYTES_PER_CELL_3D_DESIGN = 320
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 VALU_ISSUE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-instructions per second, 1e12

@@ -22,11 +22,11 @@
  *     returns a message for the calling thread's last error.  No C++ exception
  *     crosses this interface.
  *   - A handle is not thread-safe; distinct handles are independent.
- *   - Launch shape: each 2-D and 3-D sweep kernel marches a wavefront over a
- *     segment of rows (planes in 3-D) whose length the library chooses from
- *     the grid size.  Three environment variables, for tuning only, set that
- *     length instead (a positive integer; anything else is ignored); results
- *     agree to rounding for any length:
+ *   - Launch shape: each 2-D sweep kernel marches a wavefront (the 3-D sweep a
+ *     workgroup of four) over a segment of rows (planes in 3-D) whose length
+ *     the library chooses from the grid size.  Three environment variables,
+ *     for tuning only, set that length instead (a positive integer; anything
+ *     else is ignored); results agree to rounding for any length:
  *       CSH_ROWS     the characteristic sweeps, read when a 2-D handle is created;
  *       CSH_KT_ROWS  the Kurganov-Tadmor step, read at every 2-D launch;
  *       CSH_PLANES   the 3-D sweep, read at every step.
@@ -315,9 +315,9 @@ const char *csh3_last_error(void);
 /*
  * Create a 3-D handle and convert W to U (validation as csh_init_state:
  * rho > 0 and a positive-definite stress, else CSH_ERR_NONPHYSICAL with the
- * handle still returned).  The handle allocates a workspace of
- * 160 nx (ny + 2) nz bytes for the y-face states of a step.  stream: the HIP
- * stream all work of the handle runs on (NULL: the null stream).
+ * handle still returned).  A step needs no workspace: the handle holds only
+ * its timestep slots and error flag.  stream: the HIP stream all work of the
+ * handle runs on (NULL: the null stream).
  */
 int csh3_init_state(csh3_grid **h, int nx, int ny, int nz, double dx, double dy, double dz, int bc_x, int bc_y,
                     int bc_z, const void *W, void *U, void *stream);

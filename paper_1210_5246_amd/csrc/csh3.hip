@@ -1,22 +1,17 @@
 // Three-dimensional sweep of the ten-moment system (FP64), gfx950.
 //
-// Two launches per step:
-//   march3_kernel  a wavefront per 60-column strip of one row y (the rows
-//                  -1 and ny included, for their y-face states), marching
-//                  along z over a segment of planes with two planes of
-//                  primitive states in registers; per cell the
-//                  characteristic MC slopes along x (lane shifts), y (the
-//                  neighbouring rows, loaded) and z, the Hancock predictor
-//                  with the transverse terms of the two other axes, the six
-//                  face states; the x-face flux by a lane shift and the z-face
-//                  flux against the previous plane's high face, so the
-//                  partial update U - dt/dx dFx - dt/dz dFz is written to
-//                  the output; the two y-face states go to a workspace
-//                  [2][10][nz][ny + 2][nx];
-//   yflux3_kernel  a thread per (x, z) column marching over a segment of
-//                  rows: each y-face HLL flux once, the end of the update and
-//                  the fused CFL reduction that sets the next timestep on the
-//                  device.
+// One launch per step, sweep3_kernel: a workgroup of four wavefronts on four
+// consecutive rows y of a 60-column strip marches along z over a segment of
+// planes with two planes of primitive states in registers.  Per cell: the
+// characteristic MC slopes along x (lane shifts), y (neighbouring rows shared
+// through LDS) and z, the Hancock predictor with the transverse terms of the
+// two other axes, the face states; the HLL fluxes of the x faces (lane
+// shift), the y faces (neighbouring rows' states through LDS) and the z faces
+// (against the previous plane's high face, carried in registers); the
+// conservative update, and the fused CFL reduction that sets the next
+// timestep on the device.  The two outer rows of a workgroup supply slopes
+// and y-face states only, so each row's face states are formed by two
+// workgroups; in exchange nothing but the state itself crosses HBM.
 #include "csh3_device.h"
 #include "csh_internal.h"
 #include "cshydro.h"
@@ -34,7 +29,6 @@ namespace d3 {
 struct Args {
     const double* U;   // [10][nz][ny][nx]
     double* Unew;
-    double* FS;        // [6][10][ne], ne = (nx + 2)(ny + 2)(nz + 2)
     int n[3], bc[3];
     double h[3];
     double dt;
@@ -63,15 +57,6 @@ __device__ __forceinline__ V10 load(const double* __restrict__ U, size_t plane, 
     return x;
 }
 
-__device__ __forceinline__ V10 load_prim(const Args& p, int i, int j, int k)
-{
-    const int gi = map_index(i, p.n[0], p.bc[0]), gj = map_index(j, p.n[1], p.bc[1]);
-    const int gk = map_index(k, p.n[2], p.bc[2]);
-    const size_t plane = (size_t)p.n[0] * p.n[1] * p.n[2];
-    const V10 U = load(p.U, plane, ((size_t)gk * p.n[1] + gj) * p.n[0] + gi);
-    return to_prim(U, rcp(U.v[0]));
-}
-
 // wavefront-wide shift of a 10-vector by one lane (zero fill at the end)
 template <int D>
 __device__ __forceinline__ V10 shift(const V10& x)
@@ -82,67 +67,108 @@ __device__ __forceinline__ V10 shift(const V10& x)
     return y;
 }
 
-struct MArgs {
+// Workgroup of the sweep: four wavefronts on the rows j0 - 1 .. j0 + 2 of one
+// 60-column strip (64 lanes, two halo lanes per side), marching together
+// along z over a segment of planes; the two middle rows are the outputs.
+constexpr int kRows = 4;
+constexpr int kRowSlots = kRows + 2;  // rows j0 - 2 .. j0 + 3 of a plane, primitive
+constexpr int kFaceSlots = 4;         // low and high y-face states of rows j0, j0 + 1
+constexpr int kFluxSlots = 3;         // y-face fluxes j0 - 1/2, j0 + 1/2, j0 + 3/2
+
+struct SArgs {
     Args a;
-    double* FY;        // y-face states [2 (lo, hi)][10][nz][ny + 2][nx]
-    int nstrips, nsegs, tz;
+    int nstrips, npairs, nsegs, tz;
 };
 
-// One wavefront: 60 output columns (64 lanes, 2 halo lanes per side) of one
-// row j in [-1, ny] (the two outer rows only supply y-face states), marching
-// over planes [z0, z1).  Per plane: characteristic slopes along x (lane
-// shifts), y (the neighbouring rows, loaded) and z (three planes in
-// registers), the six face states, the x-face flux by a lane shift, the
-// z-face flux against the previous plane's high face; the partial update
-// U - dt/dx dFx - dt/dz dFz is written to Unew and the two y-face states to FY.
-__global__ __launch_bounds__(256) void march3_kernel(MArgs q)
+// 10-vectors in LDS as [slot][component][lane]: consecutive lanes, consecutive doubles
+__device__ __forceinline__ void put10(double* L, int slot, int lane, const V10& x)
 {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) L[(slot * NV + m) * 64 + lane] = x.v[m];
+}
+
+__device__ __forceinline__ V10 get10(const double* L, int slot, int lane)
+{
+    V10 x;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) x.v[m] = L[(slot * NV + m) * 64 + lane];
+    return x;
+}
+
+// One pass per step.  Per plane r every wavefront forms the characteristic
+// MC slopes of its row along x (lane shifts), y (the neighbouring rows from
+// LDS) and z (three planes in registers), the Hancock predictor with the
+// transverse terms of the two other axes and the face states; the output rows
+// publish their y-face states.  After a barrier the outer wavefronts take the
+// three y-face fluxes (wavefront 0 the faces j0 -+ 1/2, wavefront 3 the face
+// j0 + 3/2) while the output rows take their x-face flux (lane shift) and
+// z-face flux (against the previous plane's high face) and finish the cell of
+// plane r - 1 with the fused CFL reduction; every wavefront publishes its row
+// of plane r + 1 (wavefronts 0 and 3 also the rows j0 - 2 and j0 + 3, which
+// they load).  After a second barrier the output rows add the y-flux
+// difference.  Each LDS area is written and read on opposite sides of one of
+// the two barriers, so one copy of each suffices.
+__global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
+{
+    __shared__ double R[kRowSlots * NV * 64];
+    __shared__ double Y[kFaceSlots * NV * 64];
+    __shared__ double G[kFluxSlots * NV * 64];
     const Args& p = q.a;
     double t_now;
     const double dt = step_dt(p, &t_now);
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.slots[p.s_out].s_bits = 0ull;
-    const int lane = threadIdx.x & 63;
-    const long wid = (long)blockIdx.x * 4 + wave_in_block();
-    const int ey = p.n[1] + 2;
-    if (wid >= (long)q.nsegs * q.nstrips * ey) return;  // uniform per wavefront
-    const int jj = (int)(wid % ey), sx = (int)((wid / ey) % q.nstrips), sz = (int)(wid / ((long)ey * q.nstrips));
-    const int j = jj - 1;
-    const bool interior = j >= 0 && j < p.n[1];
-    const int c = sx * kStrip - 2 + lane;
-    const bool own = lane >= 2 && lane < 2 + kStrip && c < p.n[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.slots[p.s_out].t = t_now + dt;
+        p.slots[p.s_reset].s_bits = 0ull;
+        if (p.dt_log) *p.dt_log = dt;
+    }
+    const int lane = threadIdx.x & 63, w = wave_in_block();
+    // every workgroup is a whole (row pair, strip, segment), in the hardware's
+    // order (numbered XCD-aware, so that neighbouring row pairs share an L2,
+    // the sweep measured 2.5% slower)
+    const int g = (int)blockIdx.x;
+    const int gy = g % q.npairs, sx = (g / q.npairs) % q.nstrips, sz = g / (q.npairs * q.nstrips);
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int j0 = 2 * gy, j = j0 - 1 + w;
+    const bool out_wave = w == 1 || w == 2;  // wave-uniform
+    const bool out_row = out_wave && j < ny;
+    const bool loader = w == 0 || w == 3;    // also loads the row beyond its neighbour
+    const int c = sx * kStrip - 2 + lane;
+    const bool own = lane >= 2 && lane < 2 + kStrip && c < nx;
     const int gc = map_index(c, nx, p.bc[0]);
-    const int gjm = map_index(j - 1, ny, p.bc[1]), gj0 = map_index(j, ny, p.bc[1]), gjp = map_index(j + 1, ny, p.bc[1]);
+    const int gj = map_index(j, ny, p.bc[1]);
+    const int gh = map_index(w == 0 ? j0 - 2 : j0 + 3, ny, p.bc[1]);
     const size_t plane = (size_t)nx * ny, ncell = plane * nz;
-    const size_t fplane = (size_t)nx * ey, nf = fplane * nz;
     // with half slopes the tracing coefficients are dt/h (twice dt/2h)
     const double kx2 = dt / p.h[0], ky2 = dt / p.h[1], kz2 = dt / p.h[2];
-    const double cx = kx2, cz = kz2;
+    const double cx = kx2, cy = ky2, cz = kz2;
+    const double ih[3] = {1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2]};
     const int z0 = sz * q.tz, z1 = min(z0 + q.tz, nz);
+    double smax = 0.0;
+    bool bad = false;
 
-    auto cell = [&](int gj, int r) -> size_t {
-        return ((size_t)map_index(r, nz, p.bc[2]) * ny + gj) * nx + gc;
+    auto ld = [&](int row, int r) -> V10 {
+        return load(p.U, ncell, ((size_t)map_index(r, nz, p.bc[2]) * ny + row) * nx + gc);
     };
-    auto ld = [&](int gj, int r) -> V10 { return load(p.U, ncell, cell(gj, r)); };
     auto prim = [](const V10& U) -> V10 { return to_prim(U, rcp(U.v[0])); };
 
     // Window of the first step (r = z0 - 1): primitive planes z0 - 2 and
-    // z0 - 1, the conserved centre of plane z0 - 1, and the loads the step
-    // consumes, issued one step ahead (centre of plane r + 1, rows j -+ 1 of
-    // plane r): one wavefront per SIMD hides the memory latency this way.
-    V10 Wa = prim(ld(gj0, z0 - 2)), C0 = ld(gj0, z0 - 1), Wb = prim(C0);
-    V10 Cz = ld(gj0, z0), Cym = ld(gjm, z0 - 1), Cyp = ld(gjp, z0 - 1), zhi_prev, acc;
-    V10 Cym1 = ld(gjm, z0), Cyp1 = ld(gjp, z0);  // neighbour rows one plane ahead
-#pragma unroll
-    for (int m = 0; m < NV; ++m) zhi_prev.v[m] = acc.v[m] = 0.0;
+    // z0 - 1, the conserved own row of plane z0 - 1 and of plane z0 (loads
+    // run one plane ahead), the extra row of plane z0 for the two loaders; the
+    // rows of plane z0 - 1 go to LDS before the loop.
+    V10 Wa = prim(ld(gj, z0 - 2)), C0 = ld(gj, z0 - 1), Wb = prim(C0), Cz = ld(gj, z0), H{}, zhi_prev{}, acc{};
+    if (loader) {
+        H = ld(gh, z0);
+        put10(R, w == 0 ? 0 : kRowSlots - 1, lane, prim(ld(gh, z0 - 1)));
+    }
+    put10(R, w + 1, lane, Wb);
+    __syncthreads();
 
-    // plane r: Wm = plane r - 1 (refilled with plane r + 1), W0 = plane r.
-    // Ordered so that each slope and face pair dies as early as possible.
+    // plane r: Wm = plane r - 1 (refilled with plane r + 1), W0 = plane r
     auto plane_step = [&](int r, V10& Wm, const V10& W0) {
-        // the next step's loads first
-        // the neighbour rows of plane r + 2, loaded with this row's own plane r + 2
-        // (the neighbouring wavefronts load them as their own rows in the same step)
-        const V10 Cz_n = ld(gj0, r + 2), Cym_n = ld(gjm, r + 2), Cyp_n = ld(gjp, r + 2);
+        const V10 Cz_n = ld(gj, r + 2);  // the next step's loads first
+        V10 H_n{};
+        if (loader) H_n = ld(gh, r + 2);
+        const bool inner = r >= z0 && r < z1;  // a plane of the segment (not a halo plane)
         const double ir = rcp(W0.v[0]);
         double a3[3];  // fast speeds sqrt(3 P_kk / rho)
         auto coef = [&](int k, double k2, double& chi, double& clo) {
@@ -162,7 +188,7 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
         {
             const Eig<1> e = eig<1>(W0, ir);
             a3[1] = e.a;
-            dy = half_slope<1>(W0, ir, e, prim(Cym), prim(Cyp));
+            dy = half_slope<1>(W0, ir, e, get10(R, w, lane), get10(R, w + 2, lane));
             const V10 Ad = jac<1>(W0, ir, dy);
 #pragma unroll
             for (int m = 0; m < NV; ++m) base.v[m] -= ky2 * Ad.v[m];
@@ -176,57 +202,91 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
 #pragma unroll
             for (int m = 0; m < NV; ++m) base.v[m] -= kz2 * Ad.v[m];
         }
-        double ch, cl;
-        if (r >= z0 && r < z1 && own) {  // the y-face states of (c, j, r)
-            coef(1, ky2, ch, cl);
-            const size_t f = ((size_t)r * ey + jj) * nx + c;
+        double chy, cly;
+        coef(1, ky2, chy, cly);
+        if (out_wave && inner) {  // the two y-face states of an output row
+            V10 lo, hi;
 #pragma unroll
             for (int m = 0; m < NV; ++m) {
-                q.FY[m * nf + f] = base.v[m] - cl * dy.v[m];
-                q.FY[(NV + m) * nf + f] = base.v[m] + ch * dy.v[m];
+                lo.v[m] = base.v[m] - cly * dy.v[m];
+                hi.v[m] = base.v[m] + chy * dy.v[m];
+            }
+            put10(Y, 2 * (w - 1), lane, lo);
+            put10(Y, 2 * (w - 1) + 1, lane, hi);
+        }
+        __syncthreads();  // the rows of plane r are read, the y-face states written
+
+        put10(R, w + 1, lane, Wp);  // rows of plane r + 1
+        if (w == 0) {
+            put10(R, 0, lane, prim(H));
+            if (inner) {  // faces j0 - 1/2 (this row's high state) and j0 + 1/2
+                V10 hi;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) hi.v[m] = base.v[m] + chy * dy.v[m];
+                put10(G, 0, lane, hll<1>(hi, get10(Y, 0, lane)));
+                put10(G, 1, lane, hll<1>(get10(Y, 1, lane), get10(Y, 2, lane)));
+            }
+        } else if (w == 3) {
+            put10(R, kRowSlots - 1, lane, prim(H));
+            if (inner) {  // face j0 + 3/2 (this row's low state)
+                V10 lo;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) lo.v[m] = base.v[m] - cly * dy.v[m];
+                put10(G, 2, lane, hll<1>(get10(Y, 3, lane), lo));
+            }
+        } else {
+            double ch, cl;
+            coef(2, kz2, ch, cl);
+            if (r >= z0) {
+                V10 zlo;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) zlo.v[m] = base.v[m] - cl * dz.v[m];
+                const V10 Gz = hll<2>(zhi_prev, zlo);  // face r - 1/2
+                if (r > z0 && out_row) {  // finish the cell of plane r - 1
+                    V10 Un;
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) Un.v[m] = acc.v[m] - cz * Gz.v[m];
+                    if (own) {
+#pragma unroll
+                        for (int m = 0; m < NV; ++m) p.Unew[m * ncell + ((size_t)(r - 1) * ny + j) * nx + c] = Un.v[m];
+                        const V10 wn = to_prim(Un, rcp(Un.v[0]));
+                        smax = fmax(smax, signal_rate(wn, ih));
+                        bad |= !physical(wn);
+                    }
+                }
+                if (r < z1) {
+#pragma unroll
+                    for (int m = 0; m < NV; ++m) acc.v[m] = C0.v[m] + cz * Gz.v[m];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < NV; ++m) zhi_prev.v[m] = base.v[m] + ch * dz.v[m];
+            if (inner) {
+                coef(0, kx2, ch, cl);
+                V10 xlo, xhi;
+#pragma unroll
+                for (int m = 0; m < NV; ++m) {
+                    xlo.v[m] = base.v[m] - cl * dx.v[m];
+                    xhi.v[m] = base.v[m] + ch * dx.v[m];
+                }
+                const V10 F = hll<0>(xhi, shift<+1>(xlo));  // face c + 1/2
+                const V10 Fm = shift<-1>(F);
+#pragma unroll
+                for (int m = 0; m < NV; ++m) acc.v[m] -= cx * (F.v[m] - Fm.v[m]);
             }
         }
-        coef(2, kz2, ch, cl);
-        V10 zhi;
-        if (r >= z0) {
-            V10 zlo;
+        __syncthreads();  // the y-face fluxes and the rows of plane r + 1 written
+
+        if (out_wave && inner) {  // faces j -+ 1/2: fluxes w - 1 and w
+            const V10 Gm = get10(G, w - 1, lane), Gp = get10(G, w, lane);
 #pragma unroll
-            for (int m = 0; m < NV; ++m) zlo.v[m] = base.v[m] - cl * dz.v[m];
-            const V10 Gz = hll<2>(zhi_prev, zlo);  // face r - 1/2
-            if (r > z0 && interior && own) {
-#pragma unroll
-                for (int m = 0; m < NV; ++m)
-                    p.Unew[m * ncell + ((size_t)(r - 1) * ny + j) * nx + c] = acc.v[m] - cz * Gz.v[m];
-            }
-            if (r < z1) {
-#pragma unroll
-                for (int m = 0; m < NV; ++m) acc.v[m] = C0.v[m] + cz * Gz.v[m];
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < NV; ++m) zhi.v[m] = base.v[m] + ch * dz.v[m];
-        zhi_prev = zhi;
-        if (r >= z0 && r < z1) {
-            coef(0, kx2, ch, cl);
-            V10 xlo, xhi;
-#pragma unroll
-            for (int m = 0; m < NV; ++m) {
-                xlo.v[m] = base.v[m] - cl * dx.v[m];
-                xhi.v[m] = base.v[m] + ch * dx.v[m];
-            }
-            const V10 F = hll<0>(xhi, shift<+1>(xlo));  // face c + 1/2
-            const V10 Fm = shift<-1>(F);
-#pragma unroll
-            for (int m = 0; m < NV; ++m) acc.v[m] -= cx * (F.v[m] - Fm.v[m]);
+            for (int m = 0; m < NV; ++m) acc.v[m] -= cy * (Gp.v[m] - Gm.v[m]);
         }
         // advance the window: plane r + 1 takes the place of plane r - 1
         Wm = Wp;
         C0 = Cz;
         Cz = Cz_n;
-        Cym = Cym1;
-        Cyp = Cyp1;
-        Cym1 = Cym_n;
-        Cyp1 = Cyp_n;
+        H = H_n;
     };
 
     for (int r = z0 - 1; r <= z1; r += 2) {
@@ -234,63 +294,10 @@ __global__ __launch_bounds__(256) void march3_kernel(MArgs q)
         if (r + 1 > z1) break;
         plane_step(r + 1, Wb, Wa);
     }
-}
 
-// A thread per (x, z) column marching over a segment of rows: each y face's
-// flux once (the previous face's flux carried in registers), the end of the
-// update, CFL rate and validity.
-__global__ __launch_bounds__(256) void yflux3_kernel(MArgs q, int ty)
-{
-    const Args& p = q.a;
-    double t_now;
-    const double dt = step_dt(p, &t_now);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        p.slots[p.s_out].t = t_now + dt;
-        p.slots[p.s_reset].s_bits = 0ull;
-        if (p.dt_log) *p.dt_log = dt;
-    }
-    const int nx = p.n[0], ny = p.n[1], nz = p.n[2], ey = ny + 2;
-    const int nseg = (ny + ty - 1) / ty;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double smax = 0.0;
-    bool bad = false;
-    if (t < (size_t)nx * nz * nseg) {
-        const int i = (int)(t % nx), k = (int)((t / nx) % nz), sy = (int)(t / ((size_t)nx * nz));
-        const int y0 = sy * ty, y1 = min(y0 + ty, ny);
-        const size_t ncell = (size_t)nx * ny * nz, nf = (size_t)nx * ey * nz;
-        const double cy = dt / p.h[1];
-        const double ih[3] = {1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2]};
-        auto fidx = [&](int jj) { return ((size_t)k * ey + jj) * nx + i; };  // jj = j + 1
-        const double* FL = q.FY;
-        const double* FH = q.FY + (size_t)NV * nf;
-        // face y0 - 1/2: high state of row y0 - 1, low state of row y0; the
-        // face states of the next face are loaded one row ahead
-        V10 Gm = hll<1>(load(FH, nf, fidx(y0)), load(FL, nf, fidx(y0 + 1)));
-        V10 hi_n = load(FH, nf, fidx(y0 + 1)), lo_n = load(FL, nf, fidx(y0 + 2));
-        for (int j = y0; j < y1; ++j) {
-            const V10 hi = hi_n, lo = lo_n;
-            if (j + 1 < y1) {
-                hi_n = load(FH, nf, fidx(j + 2));
-                lo_n = load(FL, nf, fidx(j + 3));
-            }
-            const size_t c = ((size_t)k * ny + j) * nx + i;
-            const V10 A = load(p.Unew, ncell, c);
-            const V10 Gp = hll<1>(hi, lo);
-            V10 Un;
-#pragma unroll
-            for (int m = 0; m < NV; ++m) {
-                Un.v[m] = A.v[m] - cy * (Gp.v[m] - Gm.v[m]);
-                p.Unew[m * ncell + c] = Un.v[m];
-            }
-            const V10 wn = to_prim(Un, rcp(Un.v[0]));
-            smax = fmax(smax, signal_rate(wn, ih));
-            bad |= !physical(wn);
-            Gm = Gp;
-        }
-    }
     smax = wave_max(smax);
-    if ((threadIdx.x & 63) == 0) atomic_max_pos(&p.slots[p.s_out].s_bits, smax);
-    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(p.flag, 1);
+    if (out_wave && lane == 0) atomic_max_pos(&p.slots[p.s_out].s_bits, smax);
+    if (out_wave && __any(bad) && lane == 0) atomicOr(p.flag, 1);
 }
 
 __global__ __launch_bounds__(256) void init3_kernel(const double* __restrict__ W, double* __restrict__ U, int64_t n,
@@ -338,7 +345,6 @@ struct csh3_grid {
     hipStream_t capture = nullptr;
     Slot* slots = nullptr;
     int* flag = nullptr;
-    double* FS = nullptr;  // y-face states of the march
     int phase = 0;
     hipGraphExec_t exec = nullptr;
     int g_nsteps = -1;
@@ -367,19 +373,12 @@ size_t ncell(const csh3_grid* h)
     return (size_t)h->n[0] * h->n[1] * h->n[2];
 }
 
-// cells of the y-face workspace: the grid plus one row on each side in y
-size_t nfy(const csh3_grid* h)
-{
-    return (size_t)h->n[0] * (h->n[1] + 2) * h->n[2];
-}
-
 d3::Args args(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, double cfl, double* log,
               const double* dt_in)
 {
     d3::Args a{};
     a.U = U;
     a.Unew = Un;
-    a.FS = h->FS;
     for (int k = 0; k < 3; ++k) {
         a.n[k] = h->n[k];
         a.bc[k] = h->bc[k];
@@ -398,11 +397,10 @@ d3::Args args(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, 
     return a;
 }
 
-// z-segment length of the march: as for the rows of the 2-D sweep, the length
-// that minimises the busiest SIMD's critical path, ceil(wavefronts / 1024) x
-// (planes + 2) (one wavefront per SIMD; each re-traces two halo planes), over
-// 4..128 planes (measured at 256^3: 37 planes, 3.24 ms per step against 3.36 ms
-// for 32 and 3.29-3.45 ms for 24-128).
+// z-segment length of the sweep: as for the rows of the 2-D sweep, the length
+// that minimises the busiest CU's critical path, ceil(workgroups / 256) x
+// (planes + 2) (a workgroup of four wavefronts, one per SIMD, fills a CU;
+// each segment re-traces two halo planes), over 4..128 planes.
 int planes_per_segment(const csh3_grid* h)
 {
     if (const char* e = std::getenv("CSH_PLANES")) {  // tuning override
@@ -410,12 +408,12 @@ int planes_per_segment(const csh3_grid* h)
         if (v >= 1) return v;
     }
     const int nz = h->n[2];
-    const long per_segment = (long)((h->n[0] + csh::kStrip - 1) / csh::kStrip) * (h->n[1] + 2);
+    const long per_segment = (long)((h->n[0] + csh::kStrip - 1) / csh::kStrip) * ((h->n[1] + 1) / 2);
     int best = nz;
     long best_cost = -1;
     for (int t = 4; t <= std::min(nz, 128); ++t) {
-        const long waves = per_segment * ((nz + t - 1) / t);
-        const long cost = ((waves + 1023) / 1024) * (t + 2);
+        const long groups = per_segment * ((nz + t - 1) / t);
+        const long cost = ((groups + 255) / 256) * (t + 2);
         if (best_cost < 0 || cost < best_cost) {
             best_cost = cost;
             best = t;
@@ -427,18 +425,15 @@ int planes_per_segment(const csh3_grid* h)
 hipError_t enqueue_step3(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, double cfl, double* log,
                          hipStream_t s)
 {
-    d3::MArgs m{};
+    d3::SArgs m{};
     m.a = args(h, U, Un, dev_dt, dt, cfl, log, nullptr);
-    m.FY = h->FS;
     m.nstrips = (h->n[0] + csh::kStrip - 1) / csh::kStrip;
+    m.npairs = (h->n[1] + 1) / 2;
     m.tz = planes_per_segment(h);
     m.nsegs = (h->n[2] + m.tz - 1) / m.tz;
     h->phase = m.a.s_out;
-    const long nwaves = (long)m.nsegs * m.nstrips * (h->n[1] + 2);
-    const int ty = 32, nsegy = (h->n[1] + ty - 1) / ty;
-    const size_t ncol = (size_t)h->n[0] * h->n[2] * nsegy;
-    d3::march3_kernel<<<(unsigned)((nwaves + 3) / 4), 256, 0, s>>>(m);
-    d3::yflux3_kernel<<<(unsigned)((ncol + 255) / 256), 256, 0, s>>>(m, ty);
+    const long groups = (long)m.npairs * m.nstrips * m.nsegs;
+    d3::sweep3_kernel<<<(unsigned)groups, d3::kRows * 64, 0, s>>>(m);
     return hipGetLastError();
 }
 
@@ -507,8 +502,7 @@ extern "C" int csh3_init_state(csh3_grid** out, int nx, int ny, int nz, double d
         csh3_destroy(h);
         return code;
     };
-    if (hipMalloc(&h->slots, 3 * sizeof(Slot)) != hipSuccess || hipMalloc(&h->flag, sizeof(int)) != hipSuccess ||
-        hipMalloc(&h->FS, sizeof(double) * 2 * d3::NV * nfy(h)) != hipSuccess)
+    if (hipMalloc(&h->slots, 3 * sizeof(Slot)) != hipSuccess || hipMalloc(&h->flag, sizeof(int)) != hipSuccess)
         return cleanup(fail3(CSH_ERR_HIP, "hipMalloc of the handle's buffers failed"));
     if (hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
         return cleanup(fail3(CSH_ERR_HIP, "hipStreamCreate failed"));
@@ -628,6 +622,5 @@ extern "C" void csh3_destroy(csh3_grid* h)
     if (h->capture) (void)hipStreamDestroy(h->capture);
     if (h->slots) (void)hipFree(h->slots);
     if (h->flag) (void)hipFree(h->flag);
-    if (h->FS) (void)hipFree(h->FS);
     delete h;
 }

@@ -65,7 +65,7 @@ def test_3d_one_step(n, bc):
 @pytest.mark.parametrize("planes", [1, 2, 3])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
 def test_3d_short_segments(planes, bc, monkeypatch):
-    """z segments shorter than the march's halo planes (the CSH_PLANES
+    """z segments shorter than the sweep's halo planes (the CSH_PLANES
     override, read at each launch)."""
     W, g, h = workload((37, 11, 13), 73, bc)
     say("3d one step, planes per segment", planes, bc)
@@ -77,7 +77,7 @@ def test_3d_short_segments(planes, bc, monkeypatch):
     out = G.step(dt).cpu().numpy()
     ref = oracle.step3(g, dt, U0)
     assert rel_err(out, ref) <= 1e-12
-    # the same arithmetic per cell; which unrolled copy of the march loop takes a
+    # the same arithmetic per cell; which unrolled copy of the plane loop takes a
     # row depends on where its segment starts, and the compiler may fuse the
     # multiply-adds of the copies differently: equal to rounding
     dev = rel_err(out, default)
@@ -137,10 +137,11 @@ def test_3d_nonphysical_input_rejected():
 
 def test_3d_256_benchmark_configuration():
     """The benchmark's state and launch configuration (periodic 256^3, the
-    library's own segment length along z (37 planes at this size), 60-column
-    strips): one step compared cell by cell with the oracle on 3000 random
-    cells plus cells on the strip, row and segment seams (those of 37-plane
-    segments and, for good measure, of 32-plane ones) and the periodic wrap;
+    library's own segment length along z (128 planes at this size), 60-column
+    strips, row pairs): one step compared cell by cell with the oracle on 3000
+    random cells plus cells on the strip, row-pair and segment seams (those of
+    128-plane segments and, for good measure, of 37- and 32-plane ones) and
+    the periodic wrap;
     then ten device-timed steps keep every conserved total to round-off
     (periodic boundaries: the face fluxes telescope)."""
     n = 256
@@ -157,7 +158,8 @@ def test_3d_256_benchmark_configuration():
     cells = set(r.integers(0, n ** 3, size=3000).tolist())
     for x in (0, 1, 58, 59, 60, 61, 119, 120, 238, 239, 240, 254, 255):
         for y, z in ((0, 0), (255, 31), (128, 32), (1, 255), (37, 63), (200, 64), (254, 224), (100, 223),
-                     (3, 36), (250, 37), (64, 73), (129, 74), (5, 221), (252, 222)):
+                     (3, 36), (250, 37), (64, 73), (129, 74), (5, 221), (252, 222), (2, 127), (3, 128),
+                     (126, 126), (127, 129), (253, 0), (254, 255)):
             cells.add((z * n + y) * n + x)
     cells = np.array(sorted(cells), dtype=np.int64)
     ref = oracle.step3_cells(g, dt, U0, cells).T          # [10, ncells]
