@@ -47,7 +47,8 @@ def gpu(W, h, bc):
     return csh.Grid3(torch.from_numpy(np.ascontiguousarray(W)).to(DEV), h, bc)
 
 
-@pytest.mark.parametrize("n", [(37, 29, 23), (61, 5, 7), (7, 64, 3), (1, 9, 11), (12, 1, 2), (2, 2, 2)])
+@pytest.mark.parametrize("n", [(37, 29, 23), (61, 5, 7), (7, 64, 3), (1, 9, 11), (12, 1, 2), (2, 2, 2),
+                               (9, 6, 1), (65, 3, 1)])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (0, 1, 0), (1, 0, 1)])
 def test_3d_one_step(n, bc):
     W, g, h = workload(n, 71, bc)
