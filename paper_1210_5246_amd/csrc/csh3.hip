@@ -14,6 +14,7 @@
 // workgroups; in exchange nothing but the state itself crosses HBM.
 #include "csh3_device.h"
 #include "csh_internal.h"
+#include "csh_xcd.h"
 #include "cshydro.h"
 
 #include <hip/hip_runtime.h>
@@ -122,10 +123,11 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
         if (p.dt_log) *p.dt_log = dt;
     }
     const int lane = threadIdx.x & 63, w = wave_in_block();
-    // every workgroup is a whole (row pair, strip, segment), in the hardware's
-    // order: numbered XCD-aware, so that neighbouring row pairs share an L2,
-    // the sweep reads half the bytes past L2 but runs 3-4% slower
-    const int g = (int)blockIdx.x;
+    // every workgroup is a whole (row pair, strip, segment), numbered XCD-aware:
+    // neighbouring row pairs, which share four of their six rows, run on one
+    // L2 (2.6x fewer bytes read past L2 than in the hardware's order, for 3%
+    // more time: there the re-reads are served by the MALL)
+    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
     const int gy = g % q.npairs, sx = (g / q.npairs) % q.nstrips, sz = g / (q.npairs * q.nstrips);
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
     const int j0 = 2 * gy, j = j0 - 1 + w;

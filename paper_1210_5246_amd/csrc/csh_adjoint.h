@@ -13,6 +13,7 @@
 #pragma once
 
 #include "csh_device.h"
+#include "csh_xcd.h"
 
 namespace csh {
 
@@ -411,20 +412,6 @@ CSH_HD C kick_vjp(const C& lb, double h, double ax, double ay)
     o.mx += 2.0 * h * ax * lb.exx + h * ay * lb.exy;
     o.my += h * ax * lb.exy + 2.0 * h * ay * lb.eyy;
     return o;
-}
-
-// Logical index of the calling workgroup, XCD-aware.  The MI355X deals the
-// workgroups of a launch round-robin to its 8 XCDs (workgroup b to XCD b % 8),
-// each XCD with its own L2; renumbered this way each XCD takes one contiguous
-// range of logical workgroups, so tiles that share stencil rows run on the
-// same L2 at the same time.  A bijection of [0, nb) for any nb.  The
-// adjoint's one-thread-per-cell kernels run 10% faster with it; the
-// row-marching sweep kernels measured 4-8% slower and keep the hardware order.
-CSH_HD unsigned xcd_block(unsigned b, unsigned nb)
-{
-    constexpr unsigned kXcds = 8;
-    const unsigned x = b % kXcds, i = b / kXcds, per = nb / kXcds, rem = nb % kXcds;
-    return x * per + (x < rem ? x : rem) + i;
 }
 
 // ---- per-cell bodies of the adjoint kernels ----------------------------------------------
