@@ -136,6 +136,22 @@ def test_3d_nonphysical_input_rejected():
         gpu(W, h, (0, 0, 0))
 
 
+@pytest.mark.parametrize("row", [0, 6, 7, 13])
+def test_3d_step_flags_a_nonphysical_result(row):
+    """A negative density slipped into the input behind the handle's back
+    makes the new state non-finite around it; the sweep's validity test (on
+    whichever wavefront of its workgroup owns the row) raises the flag."""
+    W, g, h = workload((20, 14, 10), 77)
+    say("3d nonphysical step, row", row)
+    G = gpu(W, h, (0, 1, 0))
+    U = G.U.clone()
+    U[0, 5, row, 9] = -U[0, 5, row, 9]
+    with pytest.raises(csh.NonPhysicalState):
+        G.step(1e-4, U)
+    out = G.step(1e-4)                      # the handle still steps a valid state
+    assert torch.isfinite(out).all()
+
+
 def test_3d_256_benchmark_configuration():
     """The benchmark's state and launch configuration (periodic 256^3, the
     library's own segment length along z (128 planes at this size), 60-column

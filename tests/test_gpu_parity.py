@@ -69,6 +69,26 @@ def test_nonphysical_input_is_rejected():
         gpu_grid(w)
 
 
+@pytest.mark.parametrize("cell", [(0, 0), (7, 59), (33, 60), (69, 129)])
+def test_step_flags_a_nonphysical_result(cell):
+    """A negative density slipped into a step's input makes its output
+    non-finite around that cell; the sweep's fused validity test sets the
+    handle's flag, which the next synchronising call reports, and set_state
+    clears it."""
+    w = rect_periodic(130, 70, 23)
+    say("nonphysical step at", cell)
+    g = gpu_grid(w)
+    U = g.U.clone()
+    U[0, cell[0], cell[1]] = -U[0, cell[0], cell[1]]
+    g.step(1e-4, U)                         # asynchronous: no error yet
+    with pytest.raises(csh.NonPhysicalState):
+        g.last_signal_speed()
+    g.set_state(torch.from_numpy(np.ascontiguousarray(w.W)).to(DEV))
+    out = g.step(1e-4)
+    assert torch.isfinite(out).all()
+    assert g.last_signal_speed() > 0
+
+
 @pytest.mark.parametrize("shape", [(250, 77), (61, 5), (7, 130), (1, 3)])
 @pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
 def test_one_step_2d(shape, bc):
