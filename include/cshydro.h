@@ -282,6 +282,16 @@ int csh_batch_run(csh_batch *b, int nsteps, double cfl, void *U, void *U_work, d
                   int threads);
 
 /*
+ * Synchronises the batch's stream and reports whether any state a step of an
+ * earlier csh_batch_run produced was not physical (rho <= 0, stress not
+ * positive-definite, or non-finite): CSH_ERR_NONPHYSICAL, else CSH_OK.
+ * csh_batch_run is asynchronous and checks every new state on the device; the
+ * flag stays set for the life of the batch (as the non-physical flag of a
+ * grid handle until csh_set_state).
+ */
+int csh_batch_status(csh_batch *b);
+
+/*
  * Time the candidate workgroup sizes on this device for this batch (a few
  * steps each, on scratch copies of U; U is not modified), keep the fastest
  * as the batch's default and write it to *best_threads.  Synchronises.

@@ -77,6 +77,7 @@ _SIGNATURES = [
                                       ctypes.c_int, _vp, _vp, _vp]),
     ("csh_batch_run", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, ctypes.c_int]),
     ("csh_batch_autotune", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(ctypes.c_int)]),
+    ("csh_batch_status", ctypes.c_int, [_vp]),
     ("csh_batch_destroy", ctypes.c_int, [_vp]),
 ]
 
@@ -374,6 +375,11 @@ class Batch:
                                    _dev(self._work, torch.float64),
                                    _dev(dt_out, torch.float64, self.ntubes * nsteps, True), int(threads)))
         return dt_out
+
+    def check(self):
+        """Synchronise; raise NonPhysicalState if a step of an earlier run produced a
+        non-physical state (run() itself is asynchronous)."""
+        _check(lib().csh_batch_status(self._h))
 
     def autotune(self, probe_steps: int = 8, cfl: float = 0.8) -> int:
         best = ctypes.c_int()

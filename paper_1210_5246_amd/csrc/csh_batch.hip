@@ -282,6 +282,16 @@ extern "C" int csh_batch_run(csh_batch* b, int nsteps, double cfl, void* U, void
     return CSH_OK;
 }
 
+extern "C" int csh_batch_status(csh_batch* b)
+{
+    if (!b) return csh_fail(CSH_ERR_ARG, "NULL argument");
+    int flag = 0;
+    CSH_HIP(hipMemcpyAsync(&flag, b->flag, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    CSH_HIP(hipStreamSynchronize(b->stream));
+    if (flag) return csh_fail(CSH_ERR_NONPHYSICAL, "a tube's state was not physical");
+    return CSH_OK;
+}
+
 namespace {
 
 // ---- persisted choices of the autotuner --------------------------------------------------------

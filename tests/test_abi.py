@@ -40,6 +40,7 @@ def test_argument_validation_without_gpu():
     assert L.csh_run_cfl_states(None, 4, 0.8, None, None, None) == csh.CSH_ERR_ARG
     assert L.csh_fourier_amplitudes_noalloc(None, None, 0.0, 0.0, 1.0, 1.0, 4, None) == csh.CSH_ERR_ARG
     assert L.csh_batch_init(ctypes.byref(h), 0, None, 0, None, None, None) == csh.CSH_ERR_ARG
+    assert L.csh_batch_status(None) == csh.CSH_ERR_ARG
     assert L.csh3_init_state(ctypes.byref(h), 4, 0, 4, 1.0, 1.0, 1.0, 0, 0, 0, None, None, None) == csh.CSH_ERR_ARG
     assert b"nz" in L.csh3_last_error()
     assert L.csh3_init_state(ctypes.byref(h), 4, 4, 4, 1.0, 0.0, 1.0, 0, 0, 0, None, None, None) == csh.CSH_ERR_ARG

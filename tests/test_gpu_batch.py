@@ -154,3 +154,19 @@ def test_batch_equals_plain_path_per_tube():
             Ug = g.step(dt, Ug)
         got = U[:, t.offsets[j]:t.offsets[j + 1]]
         assert max_rel_error(got, Ug.cpu().numpy()) <= 1e-12
+
+
+def test_batch_status_reports_a_nonphysical_tube():
+    """run() is asynchronous and checks every new state on the device;
+    check() reports a tube that went non-physical (here a negative density
+    slipped into one tube between runs) and passes on a clean batch."""
+    t = subset(wl.tubes(), [0, 1, 2, 3])
+    say("batch status, lengths", t.lengths.tolist())
+    b = csh.Batch(torch.from_numpy(t.W).to(DEV), t.offsets)
+    b.run(5, t.cfl)
+    b.check()
+    c = int(t.offsets[2]) + int(t.lengths[2]) // 2
+    b.U[0, c] = -b.U[0, c]
+    b.run(1, t.cfl)
+    with pytest.raises(csh.NonPhysicalState):
+        b.check()

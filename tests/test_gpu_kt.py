@@ -194,6 +194,22 @@ def test_kt_fp32_close_to_fp64():
     assert err < 1e-3
 
 
+@pytest.mark.parametrize("shape,cell", [((130, 70), (0, 0)), ((130, 70), (37, 55)), ((130, 70), (69, 112)),
+                                        ((200, 1), (0, 57))])
+def test_kt_step_flags_a_nonphysical_result(shape, cell):
+    """A negative density slipped into a KT step's input (2-D: the fused two-
+    stage launch, around strip and segment seams; 1-D: the two launches) sets
+    the handle's flag; the next synchronising call reports it."""
+    w = rect_periodic(*shape, 24)
+    say("kt nonphysical step", shape, cell)
+    g = kt_grid(w)
+    U = g.U.clone()
+    U[0, cell[0], cell[1]] = -U[0, cell[0], cell[1]]
+    g.step(1e-4, U)
+    with pytest.raises(csh.NonPhysicalState):
+        g.last_signal_speed()
+
+
 def test_kt_rejects_characteristic_only_calls_and_switches_back():
     w = rect_periodic(70, 20, 45)
     say("kt scheme switching")
