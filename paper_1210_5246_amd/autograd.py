@@ -95,6 +95,7 @@ class AdjointSweep(torch.autograd.Function):
             done += k
         if dts is None:
             dts = dts_dev[:nsteps].cpu().tolist()  # one host synchronisation for the whole run
+        g.last_signal_speed()  # raises NonPhysicalState if a state of the run was not physical
         seg_dts = [dts[i:i + K] for i in range(0, nsteps, K)]
         ctx.grid = g
         ctx.ckpts = ckpts

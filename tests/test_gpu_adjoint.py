@@ -280,3 +280,17 @@ def test_gradient_512_against_finite_differences():
     assert stats[1e-9][2] <= 1e-6
     assert stats[1e-9][1] < stats[1e-6][1] / 10      # the kink errors shrink with the step
     assert stats[1e-9][0] >= 63
+
+
+def test_sweep_raises_on_a_nonphysical_run():
+    """The differentiable sweep reads the handle's validity flag at its one
+    host synchronisation: a run that blows up (C = 20) raises instead of
+    returning non-finite states to differentiate; the handle it caches is
+    cleared by the next sweep of the same geometry."""
+    w = wl.periodic(64, 2)
+    W0 = torch.from_numpy(w.W).to(DEV).requires_grad_(True)
+    say("autograd sweep at C = 20")
+    with pytest.raises(csh.NonPhysicalState):
+        cag.sweep(W0, w.dx, w.dy, nsteps=6, checkpoint_every=3, cfl=20.0)
+    U, _ = cag.sweep(W0, w.dx, w.dy, nsteps=3, checkpoint_every=3)
+    assert torch.isfinite(U).all()
