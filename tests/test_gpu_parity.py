@@ -261,6 +261,42 @@ def test_disc_4096_one_step_sampled():
     assert max_rel_error(out[:, cells], ref) <= TOL1
 
 
+def test_largest_fp64_grid_one_step_sampled():
+    """The largest square FP64 grid the library accepts: 23170^2 = 536.8 M
+    cells, one plane just under 4 GiB (byte offsets up to 4 GiB - 64 KiB),
+    periodic; the 1024^2 periodic state tiled and cut, so the periodic wrap
+    is a discontinuity.  One step against the oracle on sampled cells, among
+    them the last rows and columns and the wrap."""
+    n = 23170
+    assert n * n * 8 < 1 << 32 <= (n + 1) * (n + 1) * 8
+    base = wl.periodic(1024, 2)
+    say("largest FP64 grid: tiling the input on the host")
+    W = np.ascontiguousarray(np.tile(base.W, (1, 23, 23))[:, :n, :n])
+    og = oracle.Grid(n, n, 1.0 / n, 1.0 / n, 0, 0)
+    say("largest FP64 grid: device state")
+    g = csh.Grid(torch.from_numpy(W).to(DEV), 1.0 / n, 1.0 / n, (0, 0))
+    say("largest FP64 grid: oracle state and CFL rate")
+    U0 = oracle.cons_field(W)
+    del W
+    s = g.max_signal_speed()
+    assert s == pytest.approx(oracle.max_signal_speed(og, U0), rel=1e-14)
+    dt = 0.8 / s
+    say("largest FP64 grid: one step")
+    out = g.step(dt)
+    cells = set(sample_cells(n, n, 2000, 32).tolist())
+    for j in (n - 3, n - 2, n - 1):                      # the last rows, the wrap in y
+        for i in (0, 1, 59, 60, 61, n // 2, n - 3, n - 2, n - 1):
+            cells.add(j * n + i)
+    for j in (2, 1023, 1024, n // 2):                    # the last columns, the wrap in x
+        for i in (n - 3, n - 2, n - 1):
+            cells.add(j * n + i)
+    cells = np.array(sorted(cells), dtype=np.int64)
+    got = out.reshape(6, -1)[:, torch.from_numpy(cells).to(DEV)].cpu().numpy()
+    say("largest FP64 grid: oracle on", cells.size, "cells")
+    ref = oracle.step_cells(og, dt, U0, cells).T
+    assert max_rel_error(got, ref) <= TOL1
+
+
 def test_disc_4096_one_step_full():
     """Full-size disc (4096^2, FP64, outflow, fixed potential): one HLL step in
     the launch configuration of the benchmark against the oracle on every cell."""
