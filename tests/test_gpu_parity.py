@@ -297,6 +297,38 @@ def test_largest_fp64_grid_one_step_sampled():
     assert max_rel_error(got, ref) <= TOL1
 
 
+def test_largest_fp32_grid_translation_invariant():
+    """The largest square FP32 grid the library accepts: 32767^2 = 1.07 G
+    cells, one plane just under 4 GiB (byte offsets up to 4 GiB - 128 KiB):
+    the 1024^2 periodic state tiled and cut.  A property that holds at any
+    size: away from the cut, every cell's update with a given dt is that of
+    the same cell of the 1024^2 periodic grid with the same spacing (the
+    scheme is translation invariant); the two agree to FP32 rounding (the
+    unrolled copies of the row loop may fuse multiply-adds differently)."""
+    n, m = 32767, 1024
+    assert n * n * 4 < 1 << 32 <= (n + 1) * (n + 1) * 4
+    base = wl.periodic(m, 2)
+    small = csh.Grid(torch.from_numpy(base.W).to(DEV, torch.float32), 1.0 / n, 1.0 / n, (0, 0))
+    dt = 0.8 / small.max_signal_speed()
+    ref = small.step(dt).double()
+    say("largest FP32 grid: tiling the input on the host")
+    W = np.ascontiguousarray(np.tile(base.W.astype(np.float32), (1, 32, 32))[:, :n, :n])
+    big = csh.Grid(torch.from_numpy(W).to(DEV), 1.0 / n, 1.0 / n, (0, 0))
+    del W
+    say("largest FP32 grid: one step")
+    out = big.step(dt)
+    r = np.random.default_rng(33)
+    js = np.concatenate([r.integers(2, n - 2, 1500), [2, 3, m - 1, m, m + 1, n - 4, n - 3]])
+    iss = np.concatenate([r.integers(2, n - 2, 1500), [n - 3, n - 4, 2, 59, 60, 61, n - 3]])
+    flat = torch.from_numpy(js.astype(np.int64) * n + iss).to(DEV)
+    got = out.reshape(6, -1)[:, flat].double()
+    exp = ref.reshape(6, -1)[:, torch.from_numpy((js % m) * m + iss % m).to(DEV)]
+    scale = exp.abs().amax(dim=1, keepdim=True)
+    err = float(((got - exp).abs() / scale).max())
+    say("largest FP32 grid: max difference from the 1024^2 grid", err)
+    assert err <= 1e-6
+
+
 def test_disc_4096_one_step_full():
     """Full-size disc (4096^2, FP64, outflow, fixed potential): one HLL step in
     the launch configuration of the benchmark against the oracle on every cell."""
