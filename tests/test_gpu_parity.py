@@ -177,6 +177,34 @@ def test_hundred_steps_periodic_1024():
     assert max_rel_error(g.U.cpu().numpy(), ref) <= TOL100
 
 
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1)])
+def test_near_degenerate_stress_twenty_steps(bc):
+    """A dynamically cold direction and a nearly singular stress tensor
+    (Pyy / Pxx down to 1e-4, Pxy^2 up to 0.98 Pxx Pyy, the principal axes
+    turning across the grid): the shear and fast speeds of the two directions
+    differ by two orders of magnitude and q = Pxy / Pxx is large.  20 device-
+    timed steps against the oracle's CFL loop."""
+    nx, ny = 150, 70
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    pxx = 1.0 + 0.2 * np.cos(2 * np.pi * (X + Y))
+    pyy = pxx * (1e-4 + 0.02 * (1 + np.sin(2 * np.pi * X)) ** 2)
+    pxy = 0.99 * np.sqrt(pxx * pyy) * np.sin(2 * np.pi * (2 * X - Y))
+    u = 0.3 * np.sin(2 * np.pi * Y)
+    v = 0.05 * np.cos(2 * np.pi * X)
+    W = np.ascontiguousarray(np.stack([rho, u, v, pxx, pxy, pyy]))
+    say("near-degenerate stress 150x70 x 20, bc", bc)
+    og = oracle.Grid(nx, ny, 1.0 / nx, 1.0 / ny, bc[0], bc[1])
+    ref, dts_o = oracle.run_cfl(og, oracle.cons_field(W), nsteps=20, cfl=0.8)
+    g = csh.Grid(torch.from_numpy(W).to(DEV), 1.0 / nx, 1.0 / ny, bc)
+    dts = g.run_cfl(20, 0.8).cpu().numpy()
+    np.testing.assert_allclose(dts, dts_o, rtol=1e-12)
+    assert max_rel_error(g.U.cpu().numpy(), ref) <= TOL100
+    assert g.last_signal_speed() > 0
+
+
 def test_host_dt_steps_equal_device_cfl_run():
     w = wl.periodic(192, 26, 12)
     say("host-dt loop vs device run_cfl")
