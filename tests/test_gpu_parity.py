@@ -205,6 +205,55 @@ def test_near_degenerate_stress_twenty_steps(bc):
     assert g.last_signal_speed() > 0
 
 
+def test_uniform_state_is_a_fixed_point():
+    """A uniform moving state: every face sees the same two states and the
+    flux differences vanish, so the state is a fixed point.  The kernel adds a
+    cell's low y-face flux when it starts the cell's update and subtracts the
+    equal high one a row later, (U + a) - a, which rounds: the state stays
+    within a few units in the last place over ten device-timed steps (no
+    potential), the same in every cell."""
+    W = np.zeros((6, 33, 130))
+    W[:] = np.array([1.3, 0.4, -0.2, 0.9, 0.1, 0.5])[:, None, None]
+    g = csh.Grid(torch.from_numpy(W).to(DEV), 1.0 / 130, 1.0 / 33, (0, 0))
+    U0 = g.U.clone()
+    g.run_cfl(10, 0.8)
+    err = float(((g.U - U0).abs() / U0.abs().clamp_min(1e-300)).max())
+    say("uniform state, 10 steps, max relative change", err)
+    assert err <= 1e-14
+    assert torch.equal(g.U, g.U[:, :1, :1].expand_as(g.U))   # still uniform, bitwise
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_one_direction_profile_reduces_to_the_1d_sweep(axis):
+    """Rows (columns) that are all the same: the y (x) slopes and the
+    transverse terms vanish and the y (x) fluxes cancel exactly, so every row
+    of the 2-D step is the 1-D step of the profile (with the axes exchanged
+    for a profile along y), up to the rounding of the two kernels' multiply-
+    add contractions."""
+    n, m = 187, 9
+    x = (np.arange(n) + 0.5) / n
+    prof = np.stack([1.0 + 0.5 * np.tanh(20 * (x - 0.4)), 0.3 * np.sin(2 * np.pi * x), 0.1 * np.cos(2 * np.pi * x),
+                     1.0 + 0.3 * np.sin(4 * np.pi * x), 0.2 * np.sin(2 * np.pi * x + 1), 0.8 + 0.1 * np.cos(6 * np.pi * x)])
+    g1 = csh.Grid(torch.from_numpy(np.ascontiguousarray(prof[:, None, :])).to(DEV), 1.0 / n, 1.0, (1, 1))
+    dt = 0.8 / g1.max_signal_speed()
+    ref = g1.step(dt)[:, 0, :]
+    if axis == "x":
+        W = np.ascontiguousarray(np.repeat(prof[:, None, :], m, axis=1))
+        g2 = csh.Grid(torch.from_numpy(W).to(DEV), 1.0 / n, 0.37, (1, 0))
+        out = g2.step(dt)
+        got = out
+    else:
+        swapped = prof[[0, 2, 1, 5, 4, 3]]       # (rho, v, u, Pyy, Pxy, Pxx): the profile along y
+        W = np.ascontiguousarray(np.repeat(swapped[:, :, None], m, axis=2))
+        g2 = csh.Grid(torch.from_numpy(W).to(DEV), 0.37, 1.0 / n, (0, 1))
+        out = g2.step(dt)
+        got = out[[0, 2, 1, 5, 4, 3]].transpose(1, 2)
+    scale = ref.abs().amax(dim=1, keepdim=True)
+    for k in range(m):
+        err = float(((got[:, k, :] - ref).abs() / scale).max())
+        assert err <= 1e-14, (k, err)
+
+
 def test_host_dt_steps_equal_device_cfl_run():
     w = wl.periodic(192, 26, 12)
     say("host-dt loop vs device run_cfl")
