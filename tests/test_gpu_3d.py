@@ -119,6 +119,51 @@ def test_3d_host_loop_equals_device_run_and_replay():
     assert torch.equal(first, G2.U)
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_3d_one_axis_profile_equals_the_thin_grid(axis):
+    """A state that varies along one axis only: the slopes, transverse terms
+    and flux differences of the two other axes vanish, so every line of a
+    wide 3-D grid along that axis updates as the grid one cell thick in the
+    other two (the same kernel: for y the workgroups' rows and their LDS
+    exchange, for z the plane march, for x the lanes), up to the rounding of
+    the order in which the update adds its flux differences."""
+    n = 75
+    t = (np.arange(n) + 0.5) / n
+    prof = np.empty((10, n))
+    prof[0] = 1.0 + 0.4 * np.tanh(15 * (t - 0.5))
+    for k in range(1, 4):
+        prof[k] = 0.2 * np.sin(2 * np.pi * t + k)
+    # P = L L^T, L lower triangular with a positive diagonal: positive definite
+    L = np.zeros((3, 3, n))
+    L[0, 0], L[1, 1], L[2, 2] = 1.0 + 0.2 * np.sin(2 * np.pi * t), 0.8 + 0.1 * np.cos(4 * np.pi * t), 0.9 + 0.0 * t
+    L[1, 0], L[2, 0], L[2, 1] = 0.3 * np.sin(2 * np.pi * t), 0.2 * np.cos(2 * np.pi * t), 0.1 * np.sin(6 * np.pi * t)
+    P = np.einsum("ikn,jkn->ijn", L, L)
+    for (i, j), m in zip(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)), range(4, 10)):
+        prof[m] = P[i, j]
+    h = (0.011, 0.013, 0.017)
+    thin_shape = [1, 1, 1]
+    thin_shape[axis] = n
+    wide_shape = [6, 9, 5]
+    wide_shape[axis] = n
+    def field(shape):             # [10, nz, ny, nx] with the profile along the axis
+        idx = [None, None, None]
+        idx[2 - axis] = slice(None)
+        return np.broadcast_to(prof[(slice(None),) + tuple(idx)], (10,) + tuple(shape[::-1])).copy()
+    say("3d one-axis profile along", "xyz"[axis])
+    bc_wide = [0, 0, 0]
+    bc_wide[axis] = 1               # outflow along the profile, as on the thin grid
+    bc_wide[(axis + 1) % 3] = 1     # and on one of the uniform axes
+    Gt = gpu(field(thin_shape), h, (1, 1, 1))
+    dt = 0.8 / Gt.max_signal_speed()
+    ref = Gt.step(dt)
+    Gw = gpu(field(wide_shape), h, tuple(bc_wide))
+    out = Gw.step(dt)
+    scale = ref.abs().reshape(10, -1).amax(dim=1).clamp_min(1e-300).view(10, 1, 1, 1)
+    err = float(((out - ref.expand(out.shape)) / scale).abs().max())
+    say("max difference from the thin grid", err)
+    assert err <= 1e-14
+
+
 def test_3d_128_full_grid():
     W, g, h = workload((128, 128, 128), 74, (1, 0, 0))
     say("3d 128^3 one step (oracle ~10 s)")
