@@ -323,7 +323,8 @@ typedef struct csh3_grid csh3_grid;
 const char *csh3_last_error(void);
 
 /*
- * Create a 3-D handle and convert W to U (validation as csh_init_state:
+ * Create a 3-D handle and convert W to U (one component, nx ny nz doubles,
+ * smaller than 4 GiB; validation as csh_init_state:
  * rho > 0 and a positive-definite stress, else CSH_ERR_NONPHYSICAL with the
  * handle still returned).  A step needs no workspace: the handle holds only
  * its timestep slots and error flag.  stream: the HIP stream all work of the

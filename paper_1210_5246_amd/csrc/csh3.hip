@@ -484,8 +484,10 @@ extern "C" int csh3_init_state(csh3_grid** out, int nx, int ny, int nz, double d
     if (!out) return fail3(CSH_ERR_ARG, "h is NULL");
     *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1) return fail3(CSH_ERR_ARG, "nx, ny, nz must be >= 1");
-    if ((long long)nx * (ny + 2) * nz * 8 >= (1LL << 32))
-        return fail3(CSH_ERR_ARG, "one plane of the state must be smaller than 4 GiB");
+    // the kernels index with 64 bits; the limit is that of the 2-D path, kept for
+    // symmetry (3-D grids are tested up to 256^3)
+    if ((long long)nx * ny * nz * 8 >= (1LL << 32))
+        return fail3(CSH_ERR_ARG, "one component of the state must be smaller than 4 GiB");
     if (!(dx > 0) || !(dy > 0) || !(dz > 0)) return fail3(CSH_ERR_ARG, "cell sizes must be > 0");
     const int bcs[3] = {bc_x, bc_y, bc_z};
     for (int k = 0; k < 3; ++k)
