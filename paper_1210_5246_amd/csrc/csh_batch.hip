@@ -39,18 +39,21 @@ struct BatchArgs {
 // zero-gradient outflow index inside a tube of n cells
 __device__ __forceinline__ int clamp_cell(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 
+// Workgroup maximum; red holds two rows used alternately (parity), so a row
+// is rewritten only after the barrier of the call in between, when every
+// thread has read it: one barrier per call.
 template <int NT>
-__device__ __forceinline__ double block_max(double v, double* red)
+__device__ __forceinline__ double block_max(double v, double* red, int parity)
 {
     constexpr int NW = NT / 64;
+    double* r = red + parity * NW;
     v = wave_max(v);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
+    if ((threadIdx.x & 63) == 0) r[w] = v;
     __syncthreads();
-    double m = red[0];
+    double m = r[0];
 #pragma unroll
-    for (int k = 1; k < NW; ++k) m = fmax(m, red[k]);
-    __syncthreads();  // red[] may be reused after everyone has read it
+    for (int k = 1; k < NW; ++k) m = fmax(m, r[k]);
     return m;
 }
 
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs a)
 {
     constexpr int NW = NT / 64;
     __shared__ int s_q;
-    __shared__ double red[NW];
+    __shared__ double red[2 * NW];
     const int lane = threadIdx.x & 63, wave = wave_in_block();  // wave-uniform chunk loop
     const size_t plane = (size_t)a.N;
 
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs a)
         double s = 0.0;
         for (int i = threadIdx.x; i < n; i += NT)
             s = fmax(s, signal_rate<double, false>(to_prim(load_cons<double>(A, plane, (size_t)i)), idx, 0.0));
-        s = block_max<NT>(s, red);
+        s = block_max<NT>(s, red, 0);
 
         bool bad = false;
         for (int step = 0; step < a.nsteps; ++step) {
@@ -88,9 +91,14 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs a)
             if (threadIdx.x == 0 && a.dt_out) a.dt_out[(size_t)k * a.nsteps + step] = dt;
             const double kx = dt * idx * 0.5, cx = dt * idx;
             double smax = 0.0;
+            // the next chunk's loads are issued before this chunk's arithmetic
+            Cons<double> Unext{};
+            if (wave * kStrip < n) Unext = load_cons<double>(A, plane, (size_t)clamp_cell(wave * kStrip - 2 + lane, n));
             for (int base = wave * kStrip; base < n; base += NW * kStrip) {
                 const int c = base - 2 + lane;
-                const Cons<double> U0 = load_cons<double>(A, plane, (size_t)clamp_cell(c, n));
+                const Cons<double> U0 = Unext;
+                if (base + NW * kStrip < n)
+                    Unext = load_cons<double>(A, plane, (size_t)clamp_cell(base + NW * kStrip - 2 + lane, n));
                 const Cons<double> F = flux_1d(U0, kx);
                 const Cons<double> Un = update(U0, cx, F, lane_shift<-1>(F));
                 if (lane >= 2 && lane < 2 + kStrip && c < n) {
@@ -100,7 +108,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(BatchArgs a)
                     bad |= !physical(wn);
                 }
             }
-            s = block_max<NT>(smax, red);  // its barriers also order this step's stores before the next step's loads
+            s = block_max<NT>(smax, red, (step + 1) & 1);  // its barrier also orders this step's stores before the next step's loads
             double* t = A;
             A = B;
             B = t;
