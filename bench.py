@@ -27,10 +27,10 @@ BYTES_PER_CELL_F32 = 48
 BYTES_PER_CELL_KT_F64 = 96
 KT_CFL = 0.8
 # 3-D: 10 planes read + 10 written = 160 B per cell-update for a single pass;
-# a workgroup reads the rows j0 - 2 .. j0 + 3 for its two output rows, so each
-# row is read by three workgroups (240 B) unless the cache serves it: 320 B
+# a workgroup reads ten rows of 32 columns for six output rows of 28 columns,
+# 80 x (10/6) x (32/28) = 152 B, unless the cache serves the overlap: 232 B
 BYTES_PER_CELL_3D_MIN = 160
-BYTES_PER_CELL_3D_DESIGN = 320
+BYTES_PER_CELL_3D_DESIGN = 232
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
 VALU_ISSUE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12  # lane-instructions per second, 1e12

@@ -22,14 +22,20 @@
  *     returns a message for the calling thread's last error.  No C++ exception
  *     crosses this interface.
  *   - A handle is not thread-safe; distinct handles are independent.
- *   - Launch shape: each 2-D sweep kernel marches a wavefront (the 3-D sweep a
- *     workgroup of four) over a segment of rows (planes in 3-D) whose length
- *     the library chooses from the grid size.  Three environment variables,
- *     for tuning only, set that length instead (a positive integer; anything
- *     else is ignored); results agree to rounding for any length:
- *       CSH_ROWS     the characteristic sweeps, read when a 2-D handle is created;
- *       CSH_KT_ROWS  the Kurganov-Tadmor step, read at every 2-D launch;
- *       CSH_PLANES   the 3-D sweep, read at every step.
+ *   - Launch shape: each 2-D sweep kernel marches a wavefront over a segment
+ *     of rows whose length the library chooses from the grid size; the 3-D
+ *     sweep runs one workgroup of four wavefronts per compute unit, each
+ *     marching along z through an equal share of the grid's planes.
+ *     Environment variables, for tuning only, override these choices (a
+ *     positive integer; anything else is ignored); results agree to rounding
+ *     for any value:
+ *       CSH_ROWS     rows per segment of the characteristic sweeps, read when
+ *                    a 2-D handle is created;
+ *       CSH_KT_ROWS  rows per segment of the Kurganov-Tadmor step, read at
+ *                    every 2-D launch;
+ *       CSH_PLANES   the most planes the 3-D sweep marches in one piece, read
+ *                    at every step;
+ *       CSH_WG3      workgroups of the 3-D sweep, read at every step.
  */
 #ifndef CSHYDRO_H
 #define CSHYDRO_H

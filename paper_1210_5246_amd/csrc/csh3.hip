@@ -1,17 +1,18 @@
 // Three-dimensional sweep of the ten-moment system (FP64), gfx950.
 //
-// One launch per step, sweep3_kernel: a workgroup of four wavefronts on four
-// consecutive rows y of a 60-column strip marches along z over a segment of
-// planes with two planes of primitive states in registers.  Per cell: the
-// characteristic MC slopes along x (lane shifts), y (neighbouring rows shared
-// through LDS) and z, the Hancock predictor with the transverse terms of the
-// two other axes, the face states; the HLL fluxes of the x faces (lane
+// One launch per step, sweep3_kernel: a workgroup of four wavefronts, each
+// holding two rows y of a 28-column strip (32 lanes per row), marches along z
+// with two planes of primitive states in registers; one workgroup per CU, each
+// taking an equal share of the (strip, row group, plane) columns.  Per cell:
+// the characteristic MC slopes along x (lane shifts), y (neighbouring rows
+// shared through LDS) and z, the Hancock predictor with the transverse terms
+// of the two other axes, the face states; the HLL fluxes of the x faces (lane
 // shift), the y faces (neighbouring rows' states through LDS) and the z faces
 // (against the previous plane's high face, carried in registers); the
 // conservative update, and the fused CFL reduction that sets the next
-// timestep on the device.  The two outer rows of a workgroup supply slopes
-// and y-face states only, so each row's face states are formed by two
-// workgroups; in exchange nothing but the state itself crosses HBM.
+// timestep on the device.  Of the eight rows of a workgroup the outer two
+// supply slopes and y-face states only, so a quarter of the rows' face states
+// are formed twice; in exchange nothing but the state itself crosses HBM.
 #include "csh3_device.h"
 #include "csh_internal.h"
 #include "csh_xcd.h"
@@ -68,52 +69,62 @@ __device__ __forceinline__ V10 shift(const V10& x)
     return y;
 }
 
-// Workgroup of the sweep: four wavefronts on the rows j0 - 1 .. j0 + 2 of one
-// 60-column strip (64 lanes, two halo lanes per side), marching together
-// along z over a segment of planes; the two middle rows are the outputs.
-constexpr int kRows = 4;
-constexpr int kRowSlots = kRows + 2;  // rows j0 - 2 .. j0 + 3 of a plane, primitive
-constexpr int kFaceSlots = 4;         // low and high y-face states of rows j0, j0 + 1
-constexpr int kFluxSlots = 3;         // y-face fluxes j0 - 1/2, j0 + 1/2, j0 + 3/2
+// Workgroup of the sweep: four wavefronts, each holding two rows of one
+// 28-column strip (32 lanes per row, two halo lanes per side): wavefront w
+// the rows j0 - 1 + 2w (lanes 0-31) and j0 + 2w (lanes 32-63), so that the
+// workgroup spans the rows j0 - 1 .. j0 + 6, of which j0 .. j0 + 5 are its
+// outputs.  Every wavefront does the same work; wavefront 0 also loads the
+// rows j0 - 2 and j0 + 7 that the outer rows' y slopes need.
+constexpr int kHalf = 32;             // lanes per row
+constexpr int kStrip3 = kHalf - 4;    // output columns per row
+constexpr int kWaves = 4;
+constexpr int kRows = 2 * kWaves;     // rows j0 - 1 .. j0 + 6 of a workgroup
+constexpr int kOut = kRows - 2;       // output rows j0 .. j0 + 5
+constexpr int kRowSlots = kRows + 2;  // primitive rows j0 - 2 .. j0 + 7 of a plane
 
 struct SArgs {
     Args a;
-    int nstrips, npairs, nsegs, tz;
+    int nstrips, ngroups;  // strips of kStrip3 columns, groups of kOut rows
+    long long units;       // nstrips * ngroups * nz plane-columns, shared out evenly
+    int max_planes;        // longest run of planes taken in one piece
 };
 
-// 10-vectors in LDS as [slot][component][lane]: consecutive lanes, consecutive doubles
-__device__ __forceinline__ void put10(double* L, int slot, int lane, const V10& x)
+// 10-vectors in LDS as [row slot][component][column]: the 32 lanes of a row
+// read or write 32 consecutive doubles
+__device__ __forceinline__ void put10(double* L, int slot, int col, const V10& x)
 {
 #pragma unroll
-    for (int m = 0; m < NV; ++m) L[(slot * NV + m) * 64 + lane] = x.v[m];
+    for (int m = 0; m < NV; ++m) L[(slot * NV + m) * kHalf + col] = x.v[m];
 }
 
-__device__ __forceinline__ V10 get10(const double* L, int slot, int lane)
+__device__ __forceinline__ V10 get10(const double* L, int slot, int col)
 {
     V10 x;
 #pragma unroll
-    for (int m = 0; m < NV; ++m) x.v[m] = L[(slot * NV + m) * 64 + lane];
+    for (int m = 0; m < NV; ++m) x.v[m] = L[(slot * NV + m) * kHalf + col];
     return x;
 }
 
-// One pass per step.  Per plane r every wavefront forms the characteristic
-// MC slopes of its row along x (lane shifts), y (the neighbouring rows from
-// LDS) and z (three planes in registers), the Hancock predictor with the
-// transverse terms of the two other axes and the face states; the output rows
-// publish their y-face states.  After a barrier the outer wavefronts take the
-// three y-face fluxes (wavefront 0 the faces j0 -+ 1/2, wavefront 3 the face
-// j0 + 3/2) while the output rows take their x-face flux (lane shift) and
-// z-face flux (against the previous plane's high face) and finish the cell of
-// plane r - 1 with the fused CFL reduction; every wavefront publishes its row
-// of plane r + 1 (wavefronts 0 and 3 also the rows j0 - 2 and j0 + 3, which
-// they load).  After a second barrier the output rows add the y-flux
+// One pass per step.  The plane-columns (a strip, a group of rows, a plane;
+// numbered in the order strip, row group, plane) are dealt to the workgroups
+// as below; a workgroup marches along z through each run of planes it is
+// given.  Per plane r every lane forms the
+// characteristic MC slopes of its cell along x (lane shifts; a shift that
+// crosses from one row to the other lands on a halo lane, whose results are
+// not used), y (the neighbouring rows from LDS) and z (three planes in
+// registers), the Hancock predictor with the transverse terms of the two
+// other axes and the face states; it publishes its high y-face state, takes
+// the z-face flux against the previous plane's high face and finishes the
+// cell of plane r - 1 (store, CFL rate, validity), then the x-face flux.
+// After a barrier it publishes its row of plane r + 1 and the y flux of its
+// low face.  After a second barrier the output rows add the y-flux
 // difference.  Each LDS area is written and read on opposite sides of one of
 // the two barriers, so one copy of each suffices.
 __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
 {
-    __shared__ double R[kRowSlots * NV * 64];
-    __shared__ double Y[kFaceSlots * NV * 64];
-    __shared__ double G[kFluxSlots * NV * 64];
+    __shared__ double R[kRowSlots * NV * kHalf];  // primitive rows of plane r (then r + 1)
+    __shared__ double Y[kRows * NV * kHalf];      // high y-face state of each row
+    __shared__ double G[kRows * NV * kHalf];      // y flux at the low face of each row
     const Args& p = q.a;
     double t_now;
     const double dt = step_dt(p, &t_now);
@@ -123,183 +134,186 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
         if (p.dt_log) *p.dt_log = dt;
     }
     const int lane = threadIdx.x & 63, w = wave_in_block();
-    // every workgroup is a whole (row pair, strip, segment), numbered XCD-aware:
-    // neighbouring row pairs, which share four of their six rows, run on one
-    // L2 (2.6x fewer bytes read past L2 than in the hardware's order, for 3%
-    // more time: there the re-reads are served by the MALL)
-    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
-    const int gy = g % q.npairs, sx = (g / q.npairs) % q.nstrips, sz = g / (q.npairs * q.nstrips);
+    const int half = lane >> 5, col = lane & (kHalf - 1);
+    const int ys = 2 * w + half;  // row slot among j0 - 1 .. j0 + 6
+    const bool loader = w == 0;   // wave-uniform
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    const int j0 = 2 * gy, j = j0 - 1 + w;
-    const bool out_wave = w == 1 || w == 2;  // wave-uniform
-    const bool out_row = out_wave && j < ny;
-    const bool loader = w == 0 || w == 3;    // also loads the row beyond its neighbour
-    const int c = sx * kStrip - 2 + lane;
-    const bool own = lane >= 2 && lane < 2 + kStrip && c < nx;
-    const int gc = map_index(c, nx, p.bc[0]);
-    const int gj = map_index(j, ny, p.bc[1]);
-    const int gh = map_index(w == 0 ? j0 - 2 : j0 + 3, ny, p.bc[1]);
     const size_t plane = (size_t)nx * ny, ncell = plane * nz;
     // with half slopes the tracing coefficients are dt/h (twice dt/2h)
     const double kx2 = dt / p.h[0], ky2 = dt / p.h[1], kz2 = dt / p.h[2];
     const double cx = kx2, cy = ky2, cz = kz2;
     const double ih[3] = {1.0 / p.h[0], 1.0 / p.h[1], 1.0 / p.h[2]};
-    const int z0 = sz * q.tz, z1 = min(z0 + q.tz, nz);
     double smax = 0.0;
     bool bad = false;
 
-    auto ld = [&](int row, int r) -> V10 {
-        return load(p.U, ncell, ((size_t)map_index(r, nz, p.bc[2]) * ny + row) * nx + gc);
-    };
-    auto prim = [](const V10& U) -> V10 { return to_prim(U, rcp(U.v[0])); };
+    // This workgroup's share of the plane-columns, in two passes.  With at
+    // least as many columns (strip, row group) as workgroups, the first pass
+    // gives each workgroup one whole column: all march in step, and the
+    // XCD-aware numbering puts neighbouring row groups, which read two rows
+    // in common, on one L2 at the same planes.  The second pass deals the
+    // remaining plane-columns in equal contiguous shares.
+    const long long g = xcd_block(blockIdx.x, gridDim.x), nwg = gridDim.x;
+    const long long ncols = q.units / nz, full = ncols >= nwg ? nwg : 0;
+    const long long rest = q.units - full * nz;
+    for (int pass = 0; pass < 2; ++pass) {
+        long long u = pass == 0 ? g * nz : full * nz + rest * g / nwg;
+        const long long u_end = pass == 0 ? (g < full ? (g + 1) * nz : g * nz) : full * nz + rest * (g + 1) / nwg;
+        while (u < u_end) {  // wave-uniform: every wavefront takes the same runs
+            const long long cidx = u / nz;
+            const int z0 = (int)(u - cidx * nz);
+            const int z1 = (int)min((long long)min(nz, z0 + q.max_planes), z0 + (u_end - u));
+            u += z1 - z0;
+            const int gy = (int)(cidx % q.ngroups), sx = (int)(cidx / q.ngroups);
+            const int j0 = kOut * gy, j = j0 - 1 + ys;
+            const bool out_row = ys >= 1 && ys <= kOut && j < ny;
+            const int c = sx * kStrip3 - 2 + col;
+            const bool own = col >= 2 && col < 2 + kStrip3 && c < nx;
+            const int gc = map_index(c, nx, p.bc[0]);
+            const int gj = map_index(j, ny, p.bc[1]);
+            const int gh = map_index(half ? j0 + kOut + 1 : j0 - 2, ny, p.bc[1]);  // wavefront 0's extra rows
 
-    // Window of the first step (r = z0 - 1): primitive planes z0 - 2 and
-    // z0 - 1, the conserved own row of plane z0 - 1 and of plane z0 (loads
-    // run one plane ahead), the extra row of plane z0 for the two loaders; the
-    // rows of plane z0 - 1 go to LDS before the loop.
-    V10 Wa = prim(ld(gj, z0 - 2)), C0 = ld(gj, z0 - 1), Wb = prim(C0), Cz = ld(gj, z0), H{}, zhi_prev{}, acc{};
-    if (loader) {
-        H = ld(gh, z0);
-        put10(R, w == 0 ? 0 : kRowSlots - 1, lane, prim(ld(gh, z0 - 1)));
-    }
-    put10(R, w + 1, lane, Wb);
-    __syncthreads();
+            auto ld = [&](int row, int r) -> V10 {
+                return load(p.U, ncell, ((size_t)map_index(r, nz, p.bc[2]) * ny + row) * nx + gc);
+            };
+            auto prim = [](const V10& U) -> V10 { return to_prim(U, rcp(U.v[0])); };
 
-    // plane r: Wm = plane r - 1 (refilled with plane r + 1), W0 = plane r
-    auto plane_step = [&](int r, V10& Wm, const V10& W0) {
-        const V10 Cz_n = ld(gj, r + 2);  // the next step's loads first
-        V10 H_n{};
-        if (loader) H_n = ld(gh, r + 2);
-        const bool inner = r >= z0 && r < z1;  // a plane of the segment (not a halo plane)
-        const double ir = rcp(W0.v[0]);
-        double a3[3];  // fast speeds sqrt(3 P_kk / rho)
-        auto coef = [&](int k, double k2, double& chi, double& clo) {
-            const double ak = a3[k], uk = W0.v[1 + k];
-            chi = 1.0 + k2 * fmin(uk + ak, 0.0);
-            clo = 1.0 - k2 * fmax(uk - ak, 0.0);
-        };
-        V10 base = W0, dz, dy, dx;  // half slopes
-        {
-            const Eig<0> e = eig<0>(W0, ir);
-            a3[0] = e.a;
-            dx = half_slope<0>(W0, ir, e, shift<-1>(W0), shift<+1>(W0));
-            const V10 Ad = jac<0>(W0, ir, dx);
-#pragma unroll
-            for (int m = 0; m < NV; ++m) base.v[m] -= kx2 * Ad.v[m];
-        }
-        {
-            const Eig<1> e = eig<1>(W0, ir);
-            a3[1] = e.a;
-            dy = half_slope<1>(W0, ir, e, get10(R, w, lane), get10(R, w + 2, lane));
-            const V10 Ad = jac<1>(W0, ir, dy);
-#pragma unroll
-            for (int m = 0; m < NV; ++m) base.v[m] -= ky2 * Ad.v[m];
-        }
-        const V10 Wp = prim(Cz);
-        {
-            const Eig<2> e = eig<2>(W0, ir);
-            a3[2] = e.a;
-            dz = half_slope<2>(W0, ir, e, Wm, Wp);
-            const V10 Ad = jac<2>(W0, ir, dz);
-#pragma unroll
-            for (int m = 0; m < NV; ++m) base.v[m] -= kz2 * Ad.v[m];
-        }
-        double chy, cly;
-        coef(1, ky2, chy, cly);
-        if (out_wave && inner) {  // the two y-face states of an output row
-            V10 lo, hi;
-#pragma unroll
-            for (int m = 0; m < NV; ++m) {
-                lo.v[m] = base.v[m] - cly * dy.v[m];
-                hi.v[m] = base.v[m] + chy * dy.v[m];
+            // Window of the first step (r = z0 - 1): primitive planes z0 - 2 and
+            // z0 - 1, the conserved own row of plane z0 - 1 and of plane z0 (loads
+            // run one plane ahead), the extra rows of plane z0 for the loader; the
+            // rows of plane z0 - 1 go to LDS before the loop.
+            V10 Wa = prim(ld(gj, z0 - 2)), C0 = ld(gj, z0 - 1), Wb = prim(C0), Cz = ld(gj, z0), H{}, zhi_prev{}, acc{};
+            if (loader) {
+                H = ld(gh, z0);
+                put10(R, half ? kRowSlots - 1 : 0, col, prim(ld(gh, z0 - 1)));
             }
-            put10(Y, 2 * (w - 1), lane, lo);
-            put10(Y, 2 * (w - 1) + 1, lane, hi);
-        }
-        __syncthreads();  // the rows of plane r are read, the y-face states written
+            put10(R, ys + 1, col, Wb);
+            __syncthreads();
 
-        put10(R, w + 1, lane, Wp);  // rows of plane r + 1
-        if (w == 0) {
-            put10(R, 0, lane, prim(H));
-            if (inner) {  // faces j0 - 1/2 (this row's high state) and j0 + 1/2
-                V10 hi;
-#pragma unroll
-                for (int m = 0; m < NV; ++m) hi.v[m] = base.v[m] + chy * dy.v[m];
-                put10(G, 0, lane, hll<1>(hi, get10(Y, 0, lane)));
-                put10(G, 1, lane, hll<1>(get10(Y, 1, lane), get10(Y, 2, lane)));
-            }
-        } else if (w == 3) {
-            put10(R, kRowSlots - 1, lane, prim(H));
-            if (inner) {  // face j0 + 3/2 (this row's low state)
-                V10 lo;
-#pragma unroll
-                for (int m = 0; m < NV; ++m) lo.v[m] = base.v[m] - cly * dy.v[m];
-                put10(G, 2, lane, hll<1>(get10(Y, 3, lane), lo));
-            }
-        } else {
-            double ch, cl;
-            coef(2, kz2, ch, cl);
-            if (r >= z0) {
-                V10 zlo;
-#pragma unroll
-                for (int m = 0; m < NV; ++m) zlo.v[m] = base.v[m] - cl * dz.v[m];
-                const V10 Gz = hll<2>(zhi_prev, zlo);  // face r - 1/2
-                if (r > z0 && out_row) {  // finish the cell of plane r - 1
-                    V10 Un;
-#pragma unroll
-                    for (int m = 0; m < NV; ++m) Un.v[m] = acc.v[m] - cz * Gz.v[m];
-                    if (own) {
-#pragma unroll
-                        for (int m = 0; m < NV; ++m) p.Unew[m * ncell + ((size_t)(r - 1) * ny + j) * nx + c] = Un.v[m];
-                        const V10 wn = to_prim(Un, rcp(Un.v[0]));
-                        smax = fmax(smax, signal_rate(wn, ih));
-                        bad |= !physical(wn);
+            // plane r: Wm = plane r - 1 (refilled with plane r + 1), W0 = plane r
+            auto plane_step = [&](int r, V10& Wm, const V10& W0) {
+                const V10 Cz_n = ld(gj, r + 2);  // the next step's loads first
+                V10 H_n{};
+                if (loader) H_n = ld(gh, r + 2);
+                const bool inner = r >= z0 && r < z1;  // a plane of the run (not a halo plane)
+                const double ir = rcp(W0.v[0]);
+                double a3[3];  // fast speeds sqrt(3 P_kk / rho)
+                auto coef = [&](int k, double k2, double& chi, double& clo) {
+                    const double ak = a3[k], uk = W0.v[1 + k];
+                    chi = 1.0 + k2 * fmin(uk + ak, 0.0);
+                    clo = 1.0 - k2 * fmax(uk - ak, 0.0);
+                };
+                V10 base = W0, dz, dy, dx;  // half slopes
+                {
+                    const Eig<0> e = eig<0>(W0, ir);
+                    a3[0] = e.a;
+                    dx = half_slope<0>(W0, ir, e, shift<-1>(W0), shift<+1>(W0));
+                    const V10 Ad = jac<0>(W0, ir, dx);
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) base.v[m] -= kx2 * Ad.v[m];
+                }
+                {
+                    const Eig<1> e = eig<1>(W0, ir);
+                    a3[1] = e.a;
+                    dy = half_slope<1>(W0, ir, e, get10(R, ys, col), get10(R, ys + 2, col));
+                    const V10 Ad = jac<1>(W0, ir, dy);
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) base.v[m] -= ky2 * Ad.v[m];
+                }
+                const V10 Wp = prim(Cz);
+                {
+                    const Eig<2> e = eig<2>(W0, ir);
+                    a3[2] = e.a;
+                    dz = half_slope<2>(W0, ir, e, Wm, Wp);
+                    const V10 Ad = jac<2>(W0, ir, dz);
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) base.v[m] -= kz2 * Ad.v[m];
+                }
+                V10 ylo;
+                {
+                    double ch, cl;
+                    coef(1, ky2, ch, cl);
+                    V10 yhi;
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) {
+                        ylo.v[m] = base.v[m] - cl * dy.v[m];
+                        yhi.v[m] = base.v[m] + ch * dy.v[m];
                     }
+                    if (inner) put10(Y, ys, col, yhi);
                 }
-                if (r < z1) {
-#pragma unroll
-                    for (int m = 0; m < NV; ++m) acc.v[m] = C0.v[m] + cz * Gz.v[m];
+                {
+                    double ch, cl;
+                    coef(2, kz2, ch, cl);
+                    if (r >= z0) {
+                        V10 zlo;
+    #pragma unroll
+                        for (int m = 0; m < NV; ++m) zlo.v[m] = base.v[m] - cl * dz.v[m];
+                        const V10 Gz = hll<2>(zhi_prev, zlo);  // face r - 1/2
+                        if (r > z0 && out_row) {  // finish the cell of plane r - 1
+                            V10 Un;
+    #pragma unroll
+                            for (int m = 0; m < NV; ++m) Un.v[m] = acc.v[m] - cz * Gz.v[m];
+                            if (own) {
+    #pragma unroll
+                                for (int m = 0; m < NV; ++m)
+                                    p.Unew[m * ncell + ((size_t)(r - 1) * ny + j) * nx + c] = Un.v[m];
+                                const V10 wn = to_prim(Un, rcp(Un.v[0]));
+                                smax = fmax(smax, signal_rate(wn, ih));
+                                bad |= !physical(wn);
+                            }
+                        }
+                        if (r < z1) {
+    #pragma unroll
+                            for (int m = 0; m < NV; ++m) acc.v[m] = C0.v[m] + cz * Gz.v[m];
+                        }
+                    }
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) zhi_prev.v[m] = base.v[m] + ch * dz.v[m];
                 }
-            }
-#pragma unroll
-            for (int m = 0; m < NV; ++m) zhi_prev.v[m] = base.v[m] + ch * dz.v[m];
-            if (inner) {
-                coef(0, kx2, ch, cl);
-                V10 xlo, xhi;
-#pragma unroll
-                for (int m = 0; m < NV; ++m) {
-                    xlo.v[m] = base.v[m] - cl * dx.v[m];
-                    xhi.v[m] = base.v[m] + ch * dx.v[m];
+                if (inner) {
+                    double ch, cl;
+                    coef(0, kx2, ch, cl);
+                    V10 xlo, xhi;
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) {
+                        xlo.v[m] = base.v[m] - cl * dx.v[m];
+                        xhi.v[m] = base.v[m] + ch * dx.v[m];
+                    }
+                    const V10 F = hll<0>(xhi, shift<+1>(xlo));  // face c + 1/2
+                    const V10 Fm = shift<-1>(F);
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) acc.v[m] -= cx * (F.v[m] - Fm.v[m]);
                 }
-                const V10 F = hll<0>(xhi, shift<+1>(xlo));  // face c + 1/2
-                const V10 Fm = shift<-1>(F);
-#pragma unroll
-                for (int m = 0; m < NV; ++m) acc.v[m] -= cx * (F.v[m] - Fm.v[m]);
+                __syncthreads();  // the rows of plane r are read, the high y-face states written
+
+                put10(R, ys + 1, col, Wp);  // rows of plane r + 1
+                if (loader) put10(R, half ? kRowSlots - 1 : 0, col, prim(H));
+                if (inner)  // face j - 1/2 (the first row's is not used)
+                    put10(G, ys, col, hll<1>(get10(Y, ys > 0 ? ys - 1 : 0, col), ylo));
+                __syncthreads();  // the y fluxes and the rows of plane r + 1 written
+
+                if (inner && out_row) {  // faces j -+ 1/2
+                    const V10 Gm = get10(G, ys, col), Gp = get10(G, ys + 1, col);
+    #pragma unroll
+                    for (int m = 0; m < NV; ++m) acc.v[m] -= cy * (Gp.v[m] - Gm.v[m]);
+                }
+                // advance the window: plane r + 1 takes the place of plane r - 1
+                Wm = Wp;
+                C0 = Cz;
+                Cz = Cz_n;
+                H = H_n;
+            };
+
+            for (int r = z0 - 1; r <= z1; r += 2) {
+                plane_step(r, Wa, Wb);
+                if (r + 1 > z1) break;
+                plane_step(r + 1, Wb, Wa);
             }
         }
-        __syncthreads();  // the y-face fluxes and the rows of plane r + 1 written
-
-        if (out_wave && inner) {  // faces j -+ 1/2: fluxes w - 1 and w
-            const V10 Gm = get10(G, w - 1, lane), Gp = get10(G, w, lane);
-#pragma unroll
-            for (int m = 0; m < NV; ++m) acc.v[m] -= cy * (Gp.v[m] - Gm.v[m]);
-        }
-        // advance the window: plane r + 1 takes the place of plane r - 1
-        Wm = Wp;
-        C0 = Cz;
-        Cz = Cz_n;
-        H = H_n;
-    };
-
-    for (int r = z0 - 1; r <= z1; r += 2) {
-        plane_step(r, Wa, Wb);
-        if (r + 1 > z1) break;
-        plane_step(r + 1, Wb, Wa);
     }
 
     smax = wave_max(smax);
-    if (out_wave && lane == 0) atomic_max_pos(&p.slots[p.s_out].s_bits, smax);
-    if (out_wave && __any(bad) && lane == 0) atomicOr(p.flag, 1);
+    if (lane == 0) atomic_max_pos(&p.slots[p.s_out].s_bits, smax);
+    if (__any(bad) && lane == 0) atomicOr(p.flag, 1);
 }
 
 __global__ __launch_bounds__(256) void init3_kernel(const double* __restrict__ W, double* __restrict__ U, int64_t n,
@@ -348,6 +362,7 @@ struct csh3_grid {
     Slot* slots = nullptr;
     int* flag = nullptr;
     int phase = 0;
+    int ncu = 256;  // compute units of the device
     hipGraphExec_t exec = nullptr;
     int g_nsteps = -1;
     double g_cfl = 0;  // arguments the cached graph of csh3_run_cfl was recorded with
@@ -399,29 +414,15 @@ d3::Args args(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, 
     return a;
 }
 
-// z-segment length of the sweep: as for the rows of the 2-D sweep, the length
-// that minimises the busiest CU's critical path, ceil(workgroups / 256) x
-// (planes + 2) (a workgroup of four wavefronts, one per SIMD, fills a CU;
-// each segment re-traces two halo planes), over 4..128 planes.
-int planes_per_segment(const csh3_grid* h)
+// Workgroups of the sweep: one per CU (four wavefronts at one per SIMD fill
+// a CU), each taking whole columns of planes and then an equal share of the
+// rest, so that every CU marches the same number of planes (plus two halo
+// planes per run).
+long long sweep_units(const csh3_grid* h)
 {
-    if (const char* e = std::getenv("CSH_PLANES")) {  // tuning override
-        const int v = std::atoi(e);
-        if (v >= 1) return v;
-    }
-    const int nz = h->n[2];
-    const long per_segment = (long)((h->n[0] + csh::kStrip - 1) / csh::kStrip) * ((h->n[1] + 1) / 2);
-    int best = nz;
-    long best_cost = -1;
-    for (int t = 4; t <= std::min(nz, 128); ++t) {
-        const long groups = per_segment * ((nz + t - 1) / t);
-        const long cost = ((groups + 255) / 256) * (t + 2);
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
-            best = t;
-        }
-    }
-    return best;
+    const long long nstrips = (h->n[0] + d3::kStrip3 - 1) / d3::kStrip3;
+    const long long ngroups = (h->n[1] + d3::kOut - 1) / d3::kOut;
+    return nstrips * ngroups * h->n[2];
 }
 
 hipError_t enqueue_step3(csh3_grid* h, const double* U, double* Un, int dev_dt, double dt, double cfl, double* log,
@@ -429,13 +430,22 @@ hipError_t enqueue_step3(csh3_grid* h, const double* U, double* Un, int dev_dt, 
 {
     d3::SArgs m{};
     m.a = args(h, U, Un, dev_dt, dt, cfl, log, nullptr);
-    m.nstrips = (h->n[0] + csh::kStrip - 1) / csh::kStrip;
-    m.npairs = (h->n[1] + 1) / 2;
-    m.tz = planes_per_segment(h);
-    m.nsegs = (h->n[2] + m.tz - 1) / m.tz;
+    m.nstrips = (h->n[0] + d3::kStrip3 - 1) / d3::kStrip3;
+    m.ngroups = (h->n[1] + d3::kOut - 1) / d3::kOut;
+    m.units = sweep_units(h);
+    m.max_planes = h->n[2];
+    if (const char* e = std::getenv("CSH_PLANES")) {  // longest run in one piece (seam tests)
+        const int v = std::atoi(e);
+        if (v >= 1) m.max_planes = v;
+    }
+    long long wg = h->ncu;
+    if (const char* e = std::getenv("CSH_WG3")) {  // tuning override
+        const int v = std::atoi(e);
+        if (v >= 1) wg = v;
+    }
+    wg = std::min(wg, m.units);
     h->phase = m.a.s_out;
-    const long groups = (long)m.npairs * m.nstrips * m.nsegs;
-    d3::sweep3_kernel<<<(unsigned)groups, d3::kRows * 64, 0, s>>>(m);
+    d3::sweep3_kernel<<<(unsigned)wg, d3::kWaves * 64, 0, s>>>(m);
     return hipGetLastError();
 }
 
@@ -502,6 +512,12 @@ extern "C" int csh3_init_state(csh3_grid** out, int nx, int ny, int nz, double d
     h->h[2] = dz;
     for (int k = 0; k < 3; ++k) h->bc[k] = bcs[k];
     h->stream = static_cast<hipStream_t>(stream);
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            h->ncu = ncu;
+    }
     auto cleanup = [&](int code) {
         csh3_destroy(h);
         return code;

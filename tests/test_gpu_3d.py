@@ -48,7 +48,7 @@ def gpu(W, h, bc):
 
 
 @pytest.mark.parametrize("n", [(37, 29, 23), (61, 5, 7), (7, 64, 3), (1, 9, 11), (12, 1, 2), (2, 2, 2),
-                               (9, 6, 1), (65, 3, 1)])
+                               (9, 6, 1), (65, 3, 1), (28, 12, 5), (29, 13, 4)])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (0, 1, 0), (1, 0, 1)])
 def test_3d_one_step(n, bc):
     W, g, h = workload(n, 71, bc)
@@ -66,7 +66,7 @@ def test_3d_one_step(n, bc):
 @pytest.mark.parametrize("planes", [1, 2, 3])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
 def test_3d_short_segments(planes, bc, monkeypatch):
-    """z segments shorter than the sweep's halo planes (the CSH_PLANES
+    """Runs of planes shorter than the sweep's halo planes (the CSH_PLANES
     override, read at each launch)."""
     W, g, h = workload((37, 11, 13), 73, bc)
     say("3d one step, planes per segment", planes, bc)
@@ -83,6 +83,30 @@ def test_3d_short_segments(planes, bc, monkeypatch):
     # multiply-adds of the copies differently: equal to rounding
     dev = rel_err(out, default)
     say("difference from the default segment length:", dev)
+    assert dev <= 1e-14
+    assert G.last_signal_speed() == pytest.approx(oracle.max_signal_speed3(g, ref), rel=1e-13)
+
+
+@pytest.mark.parametrize("wg", [1, 3, 5, 37, 52])
+def test_3d_workgroup_shares(wg, monkeypatch):
+    """The plane-columns dealt to other numbers of workgroups (the CSH_WG3
+    override). Here 4 columns (2 strips x 2 row groups) of 13 planes: one or
+    three workgroups take whole columns first and share the rest; five and
+    more take only shares, which start and end inside a column and span
+    columns; 52 workgroups take one plane each."""
+    bc = (0, 1, 0)
+    W, g, h = workload((37, 11, 13), 78, bc)
+    say("3d one step, workgroups", wg)
+    G = gpu(W, h, bc)
+    U0 = oracle.cons3_field(W)
+    dt = 0.8 / oracle.max_signal_speed3(g, U0)
+    default = G.step(dt).cpu().numpy()
+    monkeypatch.setenv("CSH_WG3", str(wg))
+    out = G.step(dt).cpu().numpy()
+    ref = oracle.step3(g, dt, U0)
+    assert rel_err(out, ref) <= 1e-12
+    dev = rel_err(out, default)
+    say("difference from the default shares:", dev)
     assert dev <= 1e-14
     assert G.last_signal_speed() == pytest.approx(oracle.max_signal_speed3(g, ref), rel=1e-13)
 
@@ -181,11 +205,12 @@ def test_3d_nonphysical_input_rejected():
         gpu(W, h, (0, 0, 0))
 
 
-@pytest.mark.parametrize("row", [0, 6, 7, 13])
+@pytest.mark.parametrize("row", [0, 1, 2, 9, 10, 11, 13])
 def test_3d_step_flags_a_nonphysical_result(row):
     """A negative density slipped into the input behind the handle's back
     makes the new state non-finite around it; the sweep's validity test (on
-    whichever wavefront of its workgroup owns the row) raises the flag."""
+    whichever wavefront and half of its workgroup owns the row: the rows
+    6k .. 6k + 5 of a group sit on the six output halves) raises the flag."""
     W, g, h = workload((20, 14, 10), 77)
     say("3d nonphysical step, row", row)
     G = gpu(W, h, (0, 1, 0))
@@ -198,14 +223,15 @@ def test_3d_step_flags_a_nonphysical_result(row):
 
 
 def test_3d_256_benchmark_configuration():
-    """The benchmark's state and launch configuration (periodic 256^3, the
-    library's own segment length along z (128 planes at this size), 60-column
-    strips, row pairs): one step compared cell by cell with the oracle on 3000
-    random cells plus cells on the strip, row-pair and segment seams (those of
-    128-plane segments and, for good measure, of 37- and 32-plane ones) and
-    the periodic wrap;
-    then ten device-timed steps keep every conserved total to round-off
-    (periodic boundaries: the face fluxes telescope)."""
+    """The benchmark's state and launch configuration (periodic 256^3; 28-column
+    strips, groups of six rows, the plane-columns dealt in equal shares to one
+    workgroup per compute unit): one step compared cell by cell with the
+    oracle on 3000 random cells plus cells on the strip and row-group seams,
+    the periodic wrap and the planes where the shares of 256 workgroups (the
+    MI355X's compute units: 256 whole columns, then shares of the other 174)
+    start and end; then ten device-timed steps keep
+    every conserved total to round-off (periodic boundaries: the face fluxes
+    telescope)."""
     n = 256
     w = wl.periodic3(n, seed=7)
     say("3d 256^3 benchmark state: one step, sampled cells")
@@ -218,11 +244,22 @@ def test_3d_256_benchmark_configuration():
     out = G.step(dt).cpu().numpy().reshape(10, -1)
     r = np.random.default_rng(76)
     cells = set(r.integers(0, n ** 3, size=3000).tolist())
-    for x in (0, 1, 58, 59, 60, 61, 119, 120, 238, 239, 240, 254, 255):
-        for y, z in ((0, 0), (255, 31), (128, 32), (1, 255), (37, 63), (200, 64), (254, 224), (100, 223),
-                     (3, 36), (250, 37), (64, 73), (129, 74), (5, 221), (252, 222), (2, 127), (3, 128),
-                     (126, 126), (127, 129), (253, 0), (254, 255)):
-            cells.add((z * n + y) * n + x)
+    xs = (0, 1, 27, 28, 55, 56, 139, 140, 251, 252, 255)   # strips of 28 columns
+    ys = (0, 5, 6, 11, 12, 127, 131, 132, 251, 252, 255)   # groups of 6 rows
+    for x in xs:
+        for y in ys:
+            for z in (0, 1, 127, 128, 254, 255):
+                cells.add((z * n + y) * n + x)
+    strips, groups = (n + 27) // 28, (n + 5) // 6
+    rest = (strips * groups - 256) * n                    # after 256 whole columns
+    for k in range(0, 256, 9):                            # share boundaries
+        col, z = divmod(256 * n + rest * k // 256, n)
+        gy, sx = col % groups, col // groups
+        for dz in (-1, 0):
+            for x in (28 * sx, 28 * sx + 27):
+                for y in (6 * gy, 6 * gy + 5):
+                    if x < n and y < n:
+                        cells.add((((z + dz) % n) * n + y) * n + x)
     cells = np.array(sorted(cells), dtype=np.int64)
     ref = oracle.step3_cells(g, dt, U0, cells).T          # [10, ncells]
     got = out[:, cells]
