@@ -59,6 +59,30 @@ __device__ __forceinline__ V10 load(const double* __restrict__ U, size_t plane, 
     return x;
 }
 
+// Component bases of a state, set on the host: with one opaque base per
+// component each load or store takes a scalar base and a 32-bit offset
+struct Bases {
+    const char* in[NV];
+    char* out[NV];
+};
+
+// The ten components of cell `cell` (one component < 4 GiB)
+__device__ __forceinline__ V10 load32(const Bases& b, unsigned cell)
+{
+    const unsigned o = cell * (unsigned)sizeof(double);
+    V10 x;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) x.v[m] = *reinterpret_cast<const double*>(b.in[m] + o);
+    return x;
+}
+
+__device__ __forceinline__ void store32(const Bases& b, unsigned cell, const V10& x)
+{
+    const unsigned o = cell * (unsigned)sizeof(double);
+#pragma unroll
+    for (int m = 0; m < NV; ++m) *reinterpret_cast<double*>(b.out[m] + o) = x.v[m];
+}
+
 // wavefront-wide shift of a 10-vector by one lane (zero fill at the end)
 template <int D>
 __device__ __forceinline__ V10 shift(const V10& x)
@@ -84,6 +108,7 @@ constexpr int kRowSlots = kRows + 2;  // primitive rows j0 - 2 .. j0 + 7 of a pl
 
 struct SArgs {
     Args a;
+    Bases b;
     int nstrips, ngroups;  // strips of kStrip3 columns, groups of kOut rows
     long long units;       // nstrips * ngroups * nz plane-columns, shared out evenly
     int max_planes;        // longest run of planes taken in one piece
@@ -173,7 +198,7 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
             const int gh = map_index(half ? j0 + kOut + 1 : j0 - 2, ny, p.bc[1]);  // wavefront 0's extra rows
 
             auto ld = [&](int row, int r) -> V10 {
-                return load(p.U, ncell, ((size_t)map_index(r, nz, p.bc[2]) * ny + row) * nx + gc);
+                return load32(q.b, ((unsigned)map_index(r, nz, p.bc[2]) * ny + row) * nx + gc);
             };
             auto prim = [](const V10& U) -> V10 { return to_prim(U, rcp(U.v[0])); };
 
@@ -253,9 +278,7 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
     #pragma unroll
                             for (int m = 0; m < NV; ++m) Un.v[m] = acc.v[m] - cz * Gz.v[m];
                             if (own) {
-    #pragma unroll
-                                for (int m = 0; m < NV; ++m)
-                                    p.Unew[m * ncell + ((size_t)(r - 1) * ny + j) * nx + c] = Un.v[m];
+                                store32(q.b, ((unsigned)(r - 1) * ny + j) * nx + c, Un);
                                 const V10 wn = to_prim(Un, rcp(Un.v[0]));
                                 smax = fmax(smax, signal_rate(wn, ih));
                                 bad |= !physical(wn);
@@ -430,6 +453,10 @@ hipError_t enqueue_step3(csh3_grid* h, const double* U, double* Un, int dev_dt, 
 {
     d3::SArgs m{};
     m.a = args(h, U, Un, dev_dt, dt, cfl, log, nullptr);
+    for (int k = 0; k < d3::NV; ++k) {
+        m.b.in[k] = reinterpret_cast<const char*>(U + k * ncell(h));
+        m.b.out[k] = reinterpret_cast<char*>(Un + k * ncell(h));
+    }
     m.nstrips = (h->n[0] + d3::kStrip3 - 1) / d3::kStrip3;
     m.ngroups = (h->n[1] + d3::kOut - 1) / d3::kOut;
     m.units = sweep_units(h);
