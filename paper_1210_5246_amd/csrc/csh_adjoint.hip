@@ -104,12 +104,12 @@ __global__ __launch_bounds__(kA_THREADS) void adjoint_tileA_kernel(AdjArgs a, in
     tileA_fluxes(a, X0, Y0, t, L, xhi, yhi);
 }
 
-// Kernel B: a workgroup per tile of 64 x 8 virtual cells (a wavefront per
-// row), outputs its inner 62 x 6: the states of the tile and a ring into LDS,
-// per cell the face-state reverse pass from its FSb (its own share in
-// registers, the four to its neighbours in LDS), then per position everything
-// that lands on it, then per output the folded sum through W(U) plus lam'.
-// 155 KB of LDS.
+// Kernel B: a workgroup per tile of 32 x 16 virtual cells (two rows per
+// wavefront), outputs its inner 30 x 14: the states of the tile and a ring
+// into LDS, per cell the face-state reverse pass from its FSb (its own share
+// in registers, the four to its neighbours in LDS), then per position
+// everything that lands on it, then per output the folded sum through W(U)
+// plus lam'.  152 KB of LDS.
 __global__ __launch_bounds__(kB_THREADS) void adjoint_tileB_kernel(AdjArgs a, int tiles_x)
 {
     __shared__ double L[kB_LDS];

@@ -122,11 +122,12 @@ def dot_case(shape, bc, kick, seed):
     return W, g
 
 
-# sizes around 60- and 62-wide wavefront strips (1-D rows and 2-D rows) and
+# sizes around 60- and 62-wide wavefront strips (1-D rows), around the 2-D
+# reverse pass's tiles (32 x 8 extended cells; 30 x 14 outputs) and
 # tall/short grids; both boundary kinds, potential on and off
 DOT_CASES = [((58,), 0, 0), ((59,), 1, 1), ((60,), 0, 1), ((61,), 1, 0), ((121,), 0, 0), ((121,), 1, 1),
              ((37, 121), 0, 0), ((37, 121), 1, 1), ((61, 59), 1, 0), ((70, 130), 0, 1), ((5, 61), 1, 1),
-             ((130, 7), 0, 0)]
+             ((130, 7), 0, 0), ((29, 31), 1, 0), ((28, 60), 0, 1)]
 
 
 @pytest.mark.parametrize("shape,bc,kick", DOT_CASES)
