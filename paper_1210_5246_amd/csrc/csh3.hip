@@ -110,7 +110,7 @@ struct SArgs {
     Args a;
     Bases b;
     int nstrips, ngroups;  // strips of kStrip3 columns, groups of kOut rows
-    long long units;       // nstrips * ngroups * nz plane-columns, shared out evenly
+    long long units;       // nstrips * ngroups * nz plane-columns
     int max_planes;        // longest run of planes taken in one piece
 };
 
@@ -133,18 +133,17 @@ __device__ __forceinline__ V10 get10(const double* L, int slot, int col)
 // One pass per step.  The plane-columns (a strip, a group of rows, a plane;
 // numbered in the order strip, row group, plane) are dealt to the workgroups
 // as below; a workgroup marches along z through each run of planes it is
-// given.  Per plane r every lane forms the
-// characteristic MC slopes of its cell along x (lane shifts; a shift that
-// crosses from one row to the other lands on a halo lane, whose results are
-// not used), y (the neighbouring rows from LDS) and z (three planes in
-// registers), the Hancock predictor with the transverse terms of the two
-// other axes and the face states; it publishes its high y-face state, takes
-// the z-face flux against the previous plane's high face and finishes the
-// cell of plane r - 1 (store, CFL rate, validity), then the x-face flux.
-// After a barrier it publishes its row of plane r + 1 and the y flux of its
-// low face.  After a second barrier the output rows add the y-flux
-// difference.  Each LDS area is written and read on opposite sides of one of
-// the two barriers, so one copy of each suffices.
+// given.  Per plane r every lane forms the characteristic MC slopes of its
+// cell along x (lane shifts; a shift that crosses from one row to the other
+// lands on a halo lane, whose results are not used), y (the neighbouring rows
+// from LDS) and z (three planes in registers), the Hancock predictor with the
+// transverse terms of the two other axes and the face states; it publishes
+// its high y-face state, takes the z-face flux against the previous plane's
+// high face and finishes the cell of plane r - 1 (store, CFL rate,
+// validity), then the x-face flux.  After a barrier it publishes its row of
+// plane r + 1 and the y flux of its low face.  After a second barrier the
+// output rows add the y-flux difference.  Each LDS area is written and read
+// on opposite sides of one of the two barriers, so one copy of each suffices.
 __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
 {
     __shared__ double R[kRowSlots * NV * kHalf];  // primitive rows of plane r (then r + 1)
