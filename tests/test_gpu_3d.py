@@ -87,21 +87,24 @@ def test_3d_short_segments(planes, bc, monkeypatch):
     assert G.last_signal_speed() == pytest.approx(oracle.max_signal_speed3(g, ref), rel=1e-13)
 
 
-@pytest.mark.parametrize("wg", [1, 3, 5, 37, 52])
-def test_3d_workgroup_shares(wg, monkeypatch):
+@pytest.mark.parametrize("wg,planes", [(1, 0), (3, 0), (5, 0), (37, 0), (52, 0), (3, 2), (5, 3)])
+def test_3d_workgroup_shares(wg, planes, monkeypatch):
     """The plane-columns dealt to other numbers of workgroups (the CSH_WG3
-    override). Here 4 columns (2 strips x 2 row groups) of 13 planes: one or
-    three workgroups take whole columns first and share the rest; five and
-    more take only shares, which start and end inside a column and span
-    columns; 52 workgroups take one plane each."""
+    override), alone and with runs capped at a few planes (CSH_PLANES). Here
+    4 columns (2 strips x 2 row groups) of 13 planes: one or three
+    workgroups take whole columns first and share the rest; five and more
+    take only shares, which start and end inside a column and span columns;
+    52 workgroups take one plane each."""
     bc = (0, 1, 0)
     W, g, h = workload((37, 11, 13), 78, bc)
-    say("3d one step, workgroups", wg)
+    say("3d one step, workgroups", wg, "planes per run", planes or "all")
     G = gpu(W, h, bc)
     U0 = oracle.cons3_field(W)
     dt = 0.8 / oracle.max_signal_speed3(g, U0)
     default = G.step(dt).cpu().numpy()
     monkeypatch.setenv("CSH_WG3", str(wg))
+    if planes:
+        monkeypatch.setenv("CSH_PLANES", str(planes))
     out = G.step(dt).cpu().numpy()
     ref = oracle.step3(g, dt, U0)
     assert rel_err(out, ref) <= 1e-12
