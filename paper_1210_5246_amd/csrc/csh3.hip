@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
                     a3[0] = e.a;
                     dx = half_slope<0>(W0, ir, e, shift<-1>(W0), shift<+1>(W0));
                     const V10 Ad = jac<0>(W0, ir, dx);
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) base.v[m] -= kx2 * Ad.v[m];
                 }
                 {
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
                     a3[1] = e.a;
                     dy = half_slope<1>(W0, ir, e, get10(R, ys, col), get10(R, ys + 2, col));
                     const V10 Ad = jac<1>(W0, ir, dy);
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) base.v[m] -= ky2 * Ad.v[m];
                 }
                 const V10 Wp = prim(Cz);
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
                     a3[2] = e.a;
                     dz = half_slope<2>(W0, ir, e, Wm, Wp);
                     const V10 Ad = jac<2>(W0, ir, dz);
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) base.v[m] -= kz2 * Ad.v[m];
                 }
                 V10 ylo;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
                     double ch, cl;
                     coef(1, ky2, ch, cl);
                     V10 yhi;
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) {
                         ylo.v[m] = base.v[m] - cl * dy.v[m];
                         yhi.v[m] = base.v[m] + ch * dy.v[m];
@@ -269,12 +269,12 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
                     coef(2, kz2, ch, cl);
                     if (r >= z0) {
                         V10 zlo;
-    #pragma unroll
+#pragma unroll
                         for (int m = 0; m < NV; ++m) zlo.v[m] = base.v[m] - cl * dz.v[m];
                         const V10 Gz = hll<2>(zhi_prev, zlo);  // face r - 1/2
                         if (r > z0 && out_row) {  // finish the cell of plane r - 1
                             V10 Un;
-    #pragma unroll
+#pragma unroll
                             for (int m = 0; m < NV; ++m) Un.v[m] = acc.v[m] - cz * Gz.v[m];
                             if (own) {
                                 store32(q.b, ((unsigned)(r - 1) * ny + j) * nx + c, Un);
@@ -284,25 +284,25 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
                             }
                         }
                         if (r < z1) {
-    #pragma unroll
+#pragma unroll
                             for (int m = 0; m < NV; ++m) acc.v[m] = C0.v[m] + cz * Gz.v[m];
                         }
                     }
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) zhi_prev.v[m] = base.v[m] + ch * dz.v[m];
                 }
                 if (inner) {
                     double ch, cl;
                     coef(0, kx2, ch, cl);
                     V10 xlo, xhi;
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) {
                         xlo.v[m] = base.v[m] - cl * dx.v[m];
                         xhi.v[m] = base.v[m] + ch * dx.v[m];
                     }
                     const V10 F = hll<0>(xhi, shift<+1>(xlo));  // face c + 1/2
                     const V10 Fm = shift<-1>(F);
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) acc.v[m] -= cx * (F.v[m] - Fm.v[m]);
                 }
                 __syncthreads();  // the rows of plane r are read, the high y-face states written
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256) void sweep3_kernel(SArgs q)
 
                 if (inner && out_row) {  // faces j -+ 1/2
                     const V10 Gm = get10(G, ys, col), Gp = get10(G, ys + 1, col);
-    #pragma unroll
+#pragma unroll
                     for (int m = 0; m < NV; ++m) acc.v[m] -= cy * (Gp.v[m] - Gm.v[m]);
                 }
                 // advance the window: plane r + 1 takes the place of plane r - 1
