@@ -118,7 +118,8 @@ __global__ __launch_bounds__(kB_THREADS) void adjoint_tileB_kernel(AdjArgs a, in
     const int t = threadIdx.x;
     tileB_states(a, X0, Y0, t, L);
     __syncthreads();
-    // (loading the face-state adjoints before the staging above measured slower)
+    // (loading the face-state adjoints before the staging above, or between it
+    // and the barrier, measured slower)
     const P self = tileB_shares(a, X0, Y0, t, L, tileB_face_adjoints(a, X0, Y0, t));
     __syncthreads();
     tileB_put_total(t, tileB_total(t, self, L), L);  // the totals go to a slot no thread reads here
