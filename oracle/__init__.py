@@ -7,7 +7,7 @@ other.
 
 The arithmetic lives in ``cshoracle.c`` (plain C, FP64, built by the host
 compiler with ``-O2 -ffp-contract=off``, no fast-math, OpenMP over rows).
-This module is the ctypes shim plus a few drivers written directly from the
+This module is the ctypes shim plus a few time loops written directly from the
 paper:
 
 * ``run_cfl``        -- the time loop: dt = C / s from the state at the start
@@ -488,7 +488,7 @@ def same_branches(a: dict, b: dict) -> bool:
     return all(np.array_equal(a[k], b[k]) for k in a)
 
 
-# ---- drivers ---------------------------------------------------------------------------
+# ---- time loops ------------------------------------------------------------------------
 
 def run_cfl(g: Grid, U: np.ndarray, nsteps: int | None = None, cfl: float = 0.8,
             t_end: float | None = None, max_steps: int = 20000, scheme: str = "muscl"):

@@ -520,7 +520,7 @@ void orc_hllc(int dir, const double wl[NV], const double wr[NV], double flux[NV]
 }
 
 /* ---------------------------------------------------------------------- */
-/* Grid driver.                                                             */
+/* Stepping the whole grid.                                                 */
 /* ---------------------------------------------------------------------- */
 
 static int map_index(int i, int n, int bc)

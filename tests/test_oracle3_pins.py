@@ -6,7 +6,7 @@ the primitive Jacobian is the transformed flux Jacobian; A R = R Lambda,
 L R = I with ten eigenvalues u -+ a, u -+ c (twice), u (four times); a state
 that does not vary along z and has no z-motion or z-shear reproduces the
 pinned 2-D oracle; a tube along any axis reproduces the pinned 1-D oracle;
-conservation, free stream, permutation of the axes, the cell-by-cell driver,
+conservation, free stream, permutation of the axes, the cell-by-cell step,
 and second-order convergence of a wave across all three axes.
 """
 import math
@@ -202,7 +202,7 @@ def test_conservation_and_free_stream():
     np.testing.assert_allclose(oracle.step3(gf, 0.01, Uf), Uf, rtol=1e-14, atol=1e-14)
 
 
-def test_cells_driver_matches_grid_driver():
+def test_cells_step_matches_grid_step():
     w = wl.periodic3(10, 9, 8, seed=5)
     g = oracle.Grid3(10, 9, 8, 0.1, 0.1, 0.1, (1, 0, 1))
     U = oracle.cons3_field(w.W)
