@@ -334,7 +334,9 @@ const char *csh3_last_error(void);
  * rho > 0 and a positive-definite stress, else CSH_ERR_NONPHYSICAL with the
  * handle still returned).  A step needs no workspace: the handle holds only
  * its timestep slots and error flag.  stream: the HIP stream all work of the
- * handle runs on (NULL: the null stream).
+ * handle runs on (NULL: the null stream), on the device current at this
+ * call, whose compute-unit count the handle records (the sweep runs one
+ * workgroup per compute unit).
  */
 int csh3_init_state(csh3_grid **h, int nx, int ny, int nz, double dx, double dy, double dz, int bc_x, int bc_y,
                     int bc_z, const void *W, void *U, void *stream);
