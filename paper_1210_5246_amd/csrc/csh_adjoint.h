@@ -684,11 +684,12 @@ constexpr int kA_FX = kA_TX + 1, kA_FY = kA_TY + 1;  // face states: cells [X0, 
 constexpr int kA_NW = kA_WX * kA_WY, kA_NF = kA_FX * kA_FY;
 constexpr int kA_LDS = 6 * kA_NW + 12 * kA_NF;       // doubles of LDS: states, low x and y face states
 
-// kernel B: a tile of kB_W x kB_H virtual cells (two rows per wavefront), the
-// outputs its inner (kB_W - 2) x (kB_H - 2) cells.  32 x 16 rather than 64 x 8:
-// a smaller ring (82% of the threads own an output, against 73%), and at 512^2
-// 666 tiles, three rounds of one workgroup per CU, against 774 (four rounds)
-constexpr int kB_W = 32, kB_H = 16, kB_THREADS = kB_W * kB_H;
+// kernel B: a tile of kB_W x kB_H virtual cells (four rows per wavefront),
+// the outputs its inner (kB_W - 2) x (kB_H - 2) cells.  16 x 16 rather than
+// 64 x 8: 77 KB of LDS, so two workgroups share a CU and one's barriers
+// overlap the other's work, and at 512^2 1369 tiles fill three rounds of 512
+// (64 x 8: 774 tiles, four rounds of one workgroup per CU)
+constexpr int kB_W = 16, kB_H = 16, kB_THREADS = kB_W * kB_H;
 constexpr int kB_OX = kB_W - 2, kB_OY = kB_H - 2;
 enum { SH_LEFT = 0, SH_RIGHT = 1, SH_DOWN = 2, SH_UP = 3, SH_TOT = 4 };
 constexpr int kB_SX = kB_W + 2, kB_SY = kB_H + 2, kB_NS = kB_SX * kB_SY;  // states: the tile and a ring

@@ -104,12 +104,12 @@ __global__ __launch_bounds__(kA_THREADS) void adjoint_tileA_kernel(AdjArgs a, in
     tileA_fluxes(a, X0, Y0, t, L, xhi, yhi);
 }
 
-// Kernel B: a workgroup per tile of 32 x 16 virtual cells (two rows per
-// wavefront), outputs its inner 30 x 14: the states of the tile and a ring
+// Kernel B: a workgroup per tile of 16 x 16 virtual cells (four rows per
+// wavefront), outputs its inner 14 x 14: the states of the tile and a ring
 // into LDS, per cell the face-state reverse pass from its FSb (its own share
 // in registers, the four to its neighbours in LDS), then per position
 // everything that lands on it, then per output the folded sum through W(U)
-// plus lam'.  152 KB of LDS.
+// plus lam'.  77 KB of LDS, two workgroups per CU.
 __global__ __launch_bounds__(kB_THREADS) void adjoint_tileB_kernel(AdjArgs a, int tiles_x)
 {
     __shared__ double L[kB_LDS];

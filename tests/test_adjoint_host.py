@@ -162,9 +162,10 @@ def test_xcd_renumbering_is_a_bijection(nb):
 
 
 # grids around the tiles of the two-kernel reverse pass (A: 32 x 8 extended
-# cells; B: 30 x 14 outputs) and tiny ones; every boundary combination
+# cells; B: 14 x 14 outputs) and tiny ones; every boundary combination
 @pytest.mark.parametrize("shape", [(1, 4), (4, 2), (2, 2), (3, 5), (7, 3), (61, 6), (62, 7), (63, 13), (124, 12),
-                                   (125, 31), (30, 9), (30, 14), (31, 15), (29, 13), (60, 28)])
+                                   (125, 31), (30, 9), (30, 14), (31, 15), (29, 13), (60, 28), (14, 14), (15, 15),
+                                   (13, 29), (28, 43)])
 @pytest.mark.parametrize("bc", [(0, 0), (1, 1), (0, 1), (1, 0)])
 def test_tiled_reverse_pass_equals_five_stage_pass(shape, bc):
     """The tiled reverse pass (wrap on periodic axes, folded ghost positions on
