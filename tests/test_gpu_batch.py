@@ -53,6 +53,30 @@ def test_batch_matches_oracle(threads):
         assert max_rel_error(got, ref) <= 1e-10, (j, t.lengths[j])
 
 
+@pytest.mark.parametrize("threads", [None, 1024])
+def test_full_batch_sampled_tubes_match_oracle(threads):
+    """The benchmark's batch and launch: all 512 tubes in one persistent
+    launch (the autotuner's workgroup size, and 1024), 200 steps; sampled
+    tubes (the longest, the shortest and ten at random) against the oracle
+    run tube by tube, timesteps to 1e-12 and states to 1e-10."""
+    t = wl.tubes()
+    nsteps = 200
+    b = csh.Batch(torch.from_numpy(t.W).to(DEV), t.offsets)
+    if threads is None:
+        threads = b.autotune(probe_steps=8)
+        b = csh.Batch(torch.from_numpy(t.W).to(DEV), t.offsets)  # a fresh handle and state
+    say("full batch vs oracle on sampled tubes, threads", threads)
+    dts = b.run(nsteps, t.cfl, threads=threads).cpu().numpy()
+    U = b.U.cpu().numpy()
+    r = np.random.default_rng(41)
+    ks = sorted({int(np.argmax(t.lengths)), int(np.argmin(t.lengths))} | set(r.choice(512, 10, replace=False).tolist()))
+    for k in ks:
+        ref, dts_o = oracle_tube(t, k, nsteps)
+        np.testing.assert_allclose(dts[k], dts_o, rtol=1e-12)
+        got = U[:, t.offsets[k]:t.offsets[k + 1]]
+        assert max_rel_error(got, ref) <= 1e-10, (k, t.lengths[k])
+
+
 def test_batch_edge_lengths_and_odd_steps():
     lengths = np.array([1, 2, 3, 5, 59, 60, 61, 121, 4096], dtype=np.int64)
     r = np.random.default_rng(40)
