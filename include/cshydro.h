@@ -32,10 +32,13 @@
  *       CSH_ROWS     rows per segment of the characteristic sweeps, read when
  *                    a 2-D handle is created;
  *       CSH_KT_ROWS  rows per segment of the Kurganov-Tadmor step, read at
- *                    every 2-D launch;
- *       CSH_PLANES   the most planes the 3-D sweep marches in one piece, read
- *                    at every step;
- *       CSH_WG3      workgroups of the 3-D sweep, read at every step.
+ *                    every 2-D launch (a recorded graph keeps the value it
+ *                    was recorded with);
+ *       CSH_PLANES   the most planes the 3-D sweep marches in one piece;
+ *       CSH_WG3      workgroups of the 3-D sweep;
+ *     the last two are read at every csh3_step and whenever csh3_run_cfl
+ *     records its graph (a recorded graph keeps the values it was recorded
+ *     with).
  */
 #ifndef CSHYDRO_H
 #define CSHYDRO_H
