@@ -16,7 +16,7 @@ struct FourierArgs {
     double dx, dy, x0, y0;  // cell (i, j) centred at (x0 + (i + 1/2) dx, y0 + (j + 1/2) dy)
     double X, Y;         // region [-X, X] x [-Y, Y]
     int m_max;
-    double* partials;    // [kFourierBlocks][1 + 2 m_max]
+    double* partials;    // [1 + 2 m_max][kFourierBlocks] (value-major)
     double* A;           // [m_max] amplitudes A_1..A_m_max (device)
 };
 

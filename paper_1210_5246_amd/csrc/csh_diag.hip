@@ -101,33 +101,47 @@ __global__ __launch_bounds__(kThreads) void fourier_partials(FourierArgs<T> p)
     if ((int)threadIdx.x < nv) {
         double acc = 0.0;
         for (int w = 0; w < kThreads / 64; ++w) acc += part[w][threadIdx.x];
-        p.partials[(size_t)blockIdx.x * nv + threadIdx.x] = acc;
+        p.partials[(size_t)threadIdx.x * kFourierBlocks + blockIdx.x] = acc;  // value-major
     }
 }
 
 // one thread per partial row; per value a wavefront butterfly, then the
-// wavefronts' sums added in wavefront order (a fixed order)
-__global__ __launch_bounds__(kFourierBlocks) void fourier_finish(const double* __restrict__ partials, int m_max,
+// wavefronts' sums added in wavefront order (a fixed order).  The partial sums
+// are stored value-major, so each value's loads are coalesced; with M fixed
+// at compile time the loads of eight values go out together and their
+// butterflies interleave.
+template <int M>
+__global__ __launch_bounds__(kFourierBlocks) void fourier_finish(const double* __restrict__ partials,
                                                                  double* __restrict__ A)
 {
-    constexpr int kW = kFourierBlocks / 64;
-    __shared__ double part[kW][1 + 2 * kFourierMaxM];
-    const int nv = 1 + 2 * m_max;
+    constexpr int kW = kFourierBlocks / 64, nv = 1 + 2 * M;
+    __shared__ double part[kW][nv];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const double* row = partials + (size_t)threadIdx.x * nv;
-    for (int k = 0; k < nv; ++k) {
-        const double t = wave_sum(row[k]);
-        if (lane == 0) part[wv][k] = t;
+    constexpr int kC = 8;  // values in flight at once (registers stay within the 1024-thread limit)
+#pragma unroll
+    for (int k0 = 0; k0 < nv; k0 += kC) {
+        double v[kC];
+#pragma unroll
+        for (int k = 0; k < kC; ++k)
+            if (k0 + k < nv) v[k] = partials[(size_t)(k0 + k) * kFourierBlocks + threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < kC; ++k)
+            if (k0 + k < nv) v[k] = wave_sum(v[k]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kC; ++k)
+                if (k0 + k < nv) part[wv][k0 + k] = v[k];
+        }
     }
     __syncthreads();
-    __shared__ double tot[1 + 2 * kFourierMaxM];
+    __shared__ double tot[nv];
     if ((int)threadIdx.x < nv) {
         double acc = 0.0;
         for (int w = 0; w < kW; ++w) acc += part[w][threadIdx.x];
         tot[threadIdx.x] = acc;
     }
     __syncthreads();
-    if ((int)threadIdx.x < m_max) {
+    if ((int)threadIdx.x < M) {
         const double a = tot[1 + 2 * threadIdx.x], b = tot[2 + 2 * threadIdx.x];
         A[threadIdx.x] = sqrt(a * a + b * b) / tot[0];
     }
@@ -142,14 +156,14 @@ void launch_partials(const FourierArgs<T>& a, hipStream_t s)
         if (a.m_max < M) return launch_partials<T, M - 1>(a, s);
     }
     fourier_partials<T, M><<<kFourierBlocks, kThreads, 0, s>>>(a);
+    fourier_finish<M><<<1, kFourierBlocks, 0, s>>>(a.partials, a.A);
 }
 
 template <typename T>
 hipError_t launch_fourier(const FourierArgs<T>& a, hipStream_t s)
 {
     if (a.m_max < 1 || a.m_max > kFourierMaxM) return hipErrorInvalidValue;
-    launch_partials<T, kFourierMaxM>(a, s);
-    fourier_finish<<<1, kFourierBlocks, 0, s>>>(a.partials, a.m_max, a.A);
+    launch_partials<T, kFourierMaxM>(a, s);  // the partial sums and the finishing reduction
     return hipGetLastError();
 }
 
